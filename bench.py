@@ -1,0 +1,197 @@
+"""Benchmark of the spacetime finite-element Dirac solve on one MI355X.
+
+Workload: 2+1D, 128^3 trilinear spacetime elements on [0,1]^2 x [0,1] (periodic
+space), 2-component spinor, m = 1, seeded Gaussian packet (sigma = 0.05,
+|p| in [5, 20]) mixing positive and negative energies; 4,194,304 unknowns.
+
+One step = the whole hot path on that input, already resident in HBM:
+assembly of the block-CSR operator (complex128 + complex64 values, node-block
+Jacobi inverses) and of b, then the solve to true relative residual 1e-8 with
+complex64 GMRES(50) inner cycles inside FP64 refinement (spectral
+preconditioner).  Beside the timed steps the script measures the complex128
+GMRES(50) solve of the same system, plain GMRES(50) with node-block Jacobi over
+the 100-iteration window of the paper's scaling runs, and the BSR SpMV kernels
+on their own with HIP events.  The CPU oracle is timed on the host on the same
+workload.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2+1D 128³ solve time @1e-8: FP64 GMRES vs FP32-IR+NN-FGMRES; SpMV HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def spmv_bytes(op, cs):
+    """Algorithmic bytes of one SpMV: values, column indices, row pointers,
+    x and y once each."""
+    return op.nnzb * (op.nc * op.nc * cs + 4) + 4 * (op.nrows + 1) + 2 * op.n * cs
+
+
+def time_launches(fn, reps, torch):
+    """Average duration of fn() launches on the current stream, HIP events."""
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(wl, x_gpu_list):
+    """The oracle as it stands, on the host cores: element-loop assembly and
+    GMRES(50) with the same spectral preconditioner to rtol 1e-8 on the full
+    workload.  Also returns the forward error of the GPU solutions against it."""
+    import numpy as np
+    from oracle import oracle as O
+    s = wl.spec
+    p = O.problem(s.d, s.n, s.lens, s.m, s.vkind, s.v0, s.x0, s.lw)
+    t0 = time.perf_counter()
+    A = O.Matrix(p)
+    b = A.rhs(wl.psi0)
+    x, info = A.gmres(b, restart=50, max_it=200, rtol=1e-8, pc="spectral", vbar=0.0)
+    sec = time.perf_counter() - t0
+    errs = [float(np.linalg.norm(xg - x) / np.linalg.norm(x)) for xg in x_gpu_list]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sec * 1e3, "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": "full workload: oracle element-loop assembly + GMRES(50) spectral PC to 1e-8 "
+                      "(%d iterations, relres %.2e)" % (info["iters"], info["relres"])}, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only (this build has no multi-GPU path); "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2103_14588_amd import dirac_st as D
+    from paper_2103_14588_amd import inputs as IN
+
+    torch.cuda.set_device(0)
+    wl = IN.packet_2p1(128, seed=0)
+    spec = wl.spec
+    psi0 = torch.from_numpy(wl.psi0).cuda()
+    op, b = D.assemble(spec, psi0)
+    x = torch.zeros_like(b)
+    o32 = D.make_opts(restart=50, max_it=2000, pc="spectral", precision=32, rtol=1e-8,
+                      inner_rtol=1e-5, vbar=0.0)
+    o64 = D.make_opts(restart=50, max_it=2000, pc="spectral", precision=64, rtol=1e-8, vbar=0.0)
+    work = torch.empty(max(D.workspace_bytes(op, o32), D.workspace_bytes(op, o64)), dtype=torch.uint8,
+                       device="cuda")
+
+    def step():
+        D.assemble_into(op, psi0, b)
+        x.zero_()
+        _, info = D.gmres(op, b, x, opts=o32, work=work)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    info32 = infos[-1]
+    x32 = x.clone()
+
+    # complex128 GMRES(50) on the same system (assembly excluded from both solve times)
+    def solve(o):
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, inf = D.gmres(op, b, x, opts=o, work=work)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, inf
+    solve(o64)
+    ms64, info64 = solve(o64)
+    x64 = x.clone()
+    ms32, info32b = solve(o32)
+
+    # plain GMRES(50) with node-block Jacobi: the 100-iteration window
+    obj = D.make_opts(restart=50, max_it=100, pc="bj", precision=64, rtol=1e-8)
+    ms_bj, info_bj = solve(obj)
+
+    # kernels on their own (HIP events on the launch stream)
+    reps = args.kernel_reps
+    xx = torch.randn(op.n, dtype=torch.complex128, device="cuda")
+    yy = torch.empty_like(xx)
+    xx32, yy32 = xx.to(torch.complex64), torch.empty(op.n, dtype=torch.complex64, device="cuda")
+    t_spmv64 = time_launches(lambda: D.spmv(op, xx, yy), reps, torch)
+    t_spmv32 = time_launches(lambda: D.spmv(op, xx32, yy32), reps, torch)
+    t_asm = time_launches(lambda: D.assemble_into(op, psi0, b), max(reps // 4, 2), torch)
+    pcw = torch.empty(D.workspace_bytes(op, o32), dtype=torch.uint8, device="cuda")
+    t_pc32 = time_launches(lambda: D.pc_apply(op, xx32, "spectral", 0.0, yy32, pcw), max(reps // 4, 2), torch)
+    by64, by32 = spmv_bytes(op, 16), spmv_bytes(op, 8)
+    gbs64, gbs32 = by64 / t_spmv64 / 1e6, by32 / t_spmv32 / 1e6
+    asm_bytes = op.bytes() + op.n * 16 + psi0.numel() * 16
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_step, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": "2+1D 128x128x128 Q1 spacetime Dirac, Gaussian packet sigma=0.05 seed 0; "
+                               "assemble + FP32-IR GMRES(50) (spectral PC) to relres 1e-8",
+                   "mesh_elements": spec.n, "unknowns": op.n, "blocks": op.nnzb, "restart": 50,
+                   "rtol": 1e-8},
+        "solve": {
+            "fp32_ir_ms": round(ms32, 3), "fp32_ir_iters": info32b["iters"],
+            "fp32_ir_cycles": info32b["cycles"], "fp32_ir_relres": info32b["relres"],
+            "fp64_ms": round(ms64, 3), "fp64_iters": info64["iters"], "fp64_relres": info64["relres"],
+            "speedup_fp32ir_vs_fp64": round(ms64 / ms32, 3),
+            "step_relres": info32["relres"],
+            "plain_bj_100it_ms": round(ms_bj, 3), "plain_bj_100it_relres": info_bj["relres"],
+            "plain_bj_ms_per_iter": round(ms_bj / max(info_bj["iters"], 1), 4),
+        },
+        "kernels_ms": {"spmv_c128": round(t_spmv64, 4), "spmv_c64": round(t_spmv32, 4),
+                       "assemble": round(t_asm, 4), "spectral_pc_c64": round(t_pc32, 4)},
+        "spmv": {"c128_GBps": round(gbs64, 1), "c64_GBps": round(gbs32, 1),
+                 "c128_frac": round(gbs64 / HBM_PEAK_GBS, 4), "c64_frac": round(gbs32 / HBM_PEAK_GBS, 4),
+                 "c128_bytes": by64, "c64_bytes": by32},
+        "roofline": {"kernel": "spmv_kernel<double,2,16> (BSR SpMV, complex128)", "bound": "hbm",
+                     "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": None},
+        "assembly": {"ms": round(t_asm, 4), "bytes_written": asm_bytes,
+                     "GBps": round(asm_bytes / t_asm / 1e6, 1)},
+        "memory_GB": round((op.bytes() + work.numel()) / 1e9, 3),
+    }
+    if not args.no_cpu_baseline:
+        cb, errs = cpu_baseline(wl, [x32.cpu().numpy(), x64.cpu().numpy()])
+        out["cpu_baseline"] = cb
+        out["forward_error_vs_oracle"] = {"fp32_ir": errs[0], "fp64": errs[1]}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * dirac_st.h -- C ABI of the MI355X spacetime finite-element Dirac solver.
+ *
+ * Method: "A Spacetime Finite Elements Method to Solve the Dirac Equation"
+ * (arXiv:2103.14588).  The library assembles the Galerkin operator of the
+ * Dirac equation on tensor-product Q1 spacetime elements (Sec. 2.2, App. A),
+ * removes the t = 0 test rows and moves the t = 0 columns to the right-hand
+ * side (Sec. 2.1, eq. (dirac_weakIVP); Alg. 1 steps 3-5), and solves the
+ * resulting unsymmetric complex system with restarted GMRES (Sec. 2.2,
+ * Alg. 1 step 6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller, unless
+ *   the comment says "host".  Sizes come from dirac_st_sizes() and
+ *   dirac_st_workspace_bytes().  The only device allocation the library makes
+ *   is a 4-byte stream-ordered counter inside dirac_st_assemble (freed before
+ *   it returns).  Nothing is retained after a call returns.
+ * Complex layout.  Interleaved (re, im); complex128 = two doubles, complex64 =
+ *   two floats (the layout of torch.complex128 / torch.complex64).
+ * Vector layout.  Node-major, spinor component fastest: entry (r, c) at r*nc + c
+ *   with block row r = (tau - 1) * S + s, tau = 1..n_t the time node, S the
+ *   number of spatial nodes and s = i_1 + n_1 (i_2 + n_2 i_3) the spatial node
+ *   (axis 1 fastest).  The initial field psi0 uses the same layout over the
+ *   S nodes of the t = 0 slice.
+ * Matrix layout.  Block CSR: row_ptr[nrows + 1], col_idx[nnzb] (int32, columns
+ *   ascending in each row), values [nnzb][nc][nc] row-major (entry (i, j) of a
+ *   block multiplies component j of the column node into component i of the
+ *   row node).
+ * Streams.  `stream` is a hipStream_t passed as void*; NULL is the default
+ *   stream.  dirac_st_assemble, dirac_st_spmv and dirac_st_pc_apply only enqueue
+ *   work.  The solvers enqueue on `stream` and synchronise it (they read
+ *   convergence estimates back to the host); they return when done.
+ * Errors.  Every function returns an int: DIRAC_ST_OK (0), DIRAC_ST_NOT_CONVERGED
+ *   (1, solution and statistics valid), or a negative code.  The message of the
+ *   last failure on the calling thread is dirac_st_last_error().
+ * Threads.  Calls are reentrant given distinct workspaces and output buffers.
+ */
+#ifndef DIRAC_ST_H
+#define DIRAC_ST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DIRAC_ST_OK = 0,
+  DIRAC_ST_NOT_CONVERGED = 1,
+  DIRAC_ST_EINVAL = -1,      /* invalid argument or unsupported problem */
+  DIRAC_ST_EHIP = -2,        /* a HIP runtime call failed */
+  DIRAC_ST_EBREAKDOWN = -3,  /* NaN/Inf in the iteration (e.g. in b) */
+  DIRAC_ST_ENOSPACE = -4     /* workspace smaller than dirac_st_workspace_bytes() */
+};
+
+/* Potential kinds (Sec. 4.3).  V depends on the first spatial coordinate x. */
+enum {
+  DIRAC_ST_V_NONE = 0,
+  DIRAC_ST_V_STEP = 1,   /* V = v0 for x > x0 (strict), 0 otherwise */
+  DIRAC_ST_V_SMOOTH = 2  /* V = v0/2 (1 + tanh((x - x0)/lw)) */
+};
+
+/* Preconditioners (applied on the right, so GMRES minimises the true residual). */
+enum {
+  DIRAC_ST_PC_NONE = 0,
+  DIRAC_ST_PC_BLOCK_JACOBI = 1, /* inverse of each node's nc x nc diagonal block */
+  DIRAC_ST_PC_SPECTRAL = 2      /* exact inverse of the operator with V replaced by
+                                   the constant opts.vbar (periodic uniform mesh) */
+};
+
+/* Problem: the spacetime box [0, len[0]] x [0, len[1]] x ... with n[0] time
+ * elements and n[1..d] spatial elements per axis, periodic in space.
+ *   d      spatial dimensions, 1..3 (1+1, 2+1, 3+1 of Sec. 4.1)
+ *   nc     spinor components: 2 for d = 1, 2 and 4 for d = 3
+ *   n      n[0] >= 1; n[1..d] >= 3
+ *   m      mass (hbar = c = 1, Sec. 2.1)
+ *   vkind, v0, x0, lw   scalar potential, see DIRAC_ST_V_*.  It enters the
+ *          operator as the potential energy: i d_t -> i d_t - V, i.e. the
+ *          block term -g^0 int V phi_j phi_i, integrated with 2-point
+ *          Gauss-Legendre per axis.
+ * Gamma matrices: 1+1 and 2+1 use g0 = diag(1, -1), g1 = [[0, 1], [-1, 0]]
+ * (App. A), and for 2+1 g2 = [[0, -i], [-i, 0]]; 3+1 uses the Dirac
+ * representation. */
+typedef struct {
+  int32_t d;
+  int32_t nc;
+  int32_t n[4];
+  double len[4];
+  double m;
+  int32_t vkind;
+  double v0, x0, lw;
+} dirac_st_problem;
+
+/* Assembled operator A = D_w22 (Sec. 2.1).  All arrays are caller-allocated
+ * device memory sized from dirac_st_sizes().  val32, bjinv64 and bjinv32 may be
+ * NULL (then they are not written and the features needing them are off). */
+typedef struct {
+  int32_t *row_ptr;     /* [nrows + 1] */
+  int32_t *col_idx;     /* [nnzb] */
+  void *val64;          /* [nnzb][nc][nc] complex128 */
+  void *val32;          /* [nnzb][nc][nc] complex64, RNE rounding of val64 */
+  void *bjinv64;        /* [nrows][nc][nc] complex128 inverses of diagonal blocks */
+  void *bjinv32;        /* [nrows][nc][nc] complex64 */
+  int64_t nrows, nnzb;  /* set by the caller from dirac_st_sizes() */
+  int32_t nc;           /* set by dirac_st_assemble */
+  int32_t singular_blocks; /* host, set by dirac_st_assemble when bjinv64 != NULL:
+                              diagonal blocks whose 1-norm condition number
+                              exceeds 1e12 (replaced by the identity) */
+  dirac_st_problem prob;   /* set by dirac_st_assemble; the spectral
+                              preconditioner reads the mesh from here */
+} dirac_st_bsr;
+
+typedef struct {
+  int32_t restart;    /* m, Arnoldi steps per cycle (1..64) */
+  int32_t max_it;     /* cap on the total number of Arnoldi steps */
+  int32_t pc;         /* DIRAC_ST_PC_* */
+  int32_t precision;  /* 64: complex128 GMRES.  32: complex64 inner cycles
+                         (SpMV on val32, basis and preconditioner in complex64)
+                         inside an FP64 refinement loop: every cycle starts from
+                         the FP64 true residual b - A x (val64) and adds its
+                         correction to x in FP64.  Givens rotations and the
+                         Hessenberg solve are FP64 in both modes. */
+  int32_t max_cycles; /* cap on restart cycles (refinement steps); 0 = no cap */
+  double rtol;        /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual) */
+  double inner_rtol;  /* precision 32: a cycle also ends when its estimated
+                         residual falls below inner_rtol times its starting
+                         residual (0 = run the full cycle) */
+  double vbar;        /* constant potential of DIRAC_ST_PC_SPECTRAL */
+} dirac_st_opts;
+
+typedef struct {
+  int32_t iters;        /* Arnoldi steps taken */
+  int32_t cycles;       /* restart cycles (= refinement steps for precision 32) */
+  int32_t converged;    /* 1 if the true relative residual <= rtol */
+  int32_t singular_blocks;
+  double relres;        /* true relative residual ||b - A x|| / ||b|| at exit (FP64) */
+  double est;           /* last Arnoldi residual estimate / ||b|| */
+  double ms;            /* wall time of the solve on the host clock */
+  double *history;      /* host, optional (NULL): residual estimate / ||b|| after
+                           each Arnoldi step, up to history_len entries */
+  int32_t history_len;
+} dirac_st_stats;
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *dirac_st_last_error(void);
+
+/* Host.  Number of block rows (unknown nodes, tau = 1..n_t) and stored blocks
+ * of the assembled operator: a row holds 3^(d+1) blocks, 2*3^d in the first
+ * and last time slice (3^d if n_t = 1).  Sec. 2.1-2.2. */
+int dirac_st_sizes(const dirac_st_problem *prob, int64_t *nrows, int64_t *nnzb);
+
+/* Assemble A = D_w22 into block CSR and the right-hand side b = -D_w21 psi0
+ * (Sec. 2.1, eq. (dirac_weakIVP); Sec. 2.2 element summation; App. A element
+ * matrices).  psi0: [S][nc] complex128 nodal values at t = 0 (may be NULL if
+ * b is NULL).  b: [nrows][nc] complex128 (may be NULL).  Fills A->row_ptr,
+ * col_idx, val64 and, when non-NULL, val32, bjinv64, bjinv32; sets A->nc,
+ * A->prob and A->singular_blocks (synchronises the stream to read the
+ * count when bjinv64 != NULL).  A->nrows and A->nnzb must equal
+ * dirac_st_sizes(). */
+int dirac_st_assemble(const dirac_st_problem *prob, const void *psi0, dirac_st_bsr *A, void *b,
+                      void *stream);
+
+/* y = A x (Sec. 2.2: the product inside GMRES).  prec 64: complex128 x, y and
+ * val64; prec 32: complex64 x, y and val32.  x and y must not overlap. */
+int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x, void *y, void *stream);
+
+/* z = M^{-1} v for the preconditioner `pc` (DIRAC_ST_PC_*) in precision prec
+ * (64: complex128, 32: complex64).  work: workspace of at least
+ * dirac_st_workspace_bytes(A, opts, 0) bytes for opts->pc = pc (the spectral
+ * preconditioner keeps its factorisation there; the call sets it up). */
+int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec, double vbar, const void *v,
+                      void *z, void *work, size_t work_bytes, void *stream);
+
+/* Bytes of device workspace needed by dirac_st_gmres for these options
+ * (basis of restart+1 vectors in the working precision, partial sums,
+ * Hessenberg data, preconditioner data). */
+size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *opts, int32_t flexible);
+
+/* Restarted GMRES(m) with right preconditioning (Sec. 2.2; Alg. 1 step 6):
+ * two-pass classical Gram-Schmidt, complex Givens rotations, x += M^{-1} V y at
+ * the end of each cycle, true residual recomputed in FP64 at every restart.
+ * b: [nrows][nc] complex128.  x: [nrows][nc] complex128, initial guess on
+ * entry, solution on exit.  stats: host, may be NULL.  Returns DIRAC_ST_OK,
+ * DIRAC_ST_NOT_CONVERGED (max_it or max_cycles reached), or an error
+ * (DIRAC_ST_EBREAKDOWN if NaN/Inf appears, e.g. from b). */
+int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_opts *opts,
+                   void *work, size_t work_bytes, dirac_st_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIRAC_ST_H */

@@ -1,0 +1,415 @@
+// assemble.hip -- assembly of the spacetime Q1 Dirac operator into block CSR.
+//
+// The global block coupling row node r to column node c is the sum, over the
+// elements that contain both nodes, of the element block
+//     B_e(beta, alpha) = sum_mu i g^mu D^mu - m D^0 I - g^0 P
+// (App. A, eq. (diracWeak1p1) extended per axis; Sec. 2.2 element summation).
+// On a tensor mesh every element matrix is a product of 1D factors, one per
+// axis, and the elements containing both nodes are the product of the 1D
+// element choices per axis; so the sum over elements factorises into a product
+// over axes of 1D sums.  Each GPU thread builds one block that way (a gather:
+// no atomics, deterministic), writes it in complex128 and complex64, its
+// column index, the row pointer and, for diagonal blocks, the inverse used by
+// the node-block Jacobi preconditioner.
+//
+// Rows at t = 0 are not assembled; their columns form D_w21 and are applied
+// to psi0 directly to give b = -D_w21 psi0 (Sec. 2.1, eq. (dirac_weakIVP)).
+#include <cmath>
+
+#include "common.hpp"
+
+namespace dst {
+
+struct AsmParams {
+  int d, nc, nt;
+  int n[4];
+  int64_t S, nrows, nnzb;
+  int64_t stride[4];   // spatial node strides (axis 1 fastest)
+  double h[4];
+  double M[4][2][2];   // 1D element mass  int phi_b phi_a     (row b = test)
+  double Cd[4][2][2];  // 1D element       int phi_b phi_a'
+  double m;
+  int vkind;
+  double v0, x0, lw;
+  double2 g[4][16];    // gamma^mu, row-major nc x nc
+  int c1, cint, clast, sp3;
+  int64_t off_int, off_last;
+};
+
+static void gamma_set(int d, double2 (*g)[16]) {
+  for (int mu = 0; mu < 4; mu++)
+    for (int q = 0; q < 16; q++) g[mu][q] = mk<double2>(0, 0);
+  if (d <= 2) {
+    // g0 = diag(1, -1), g1 = [[0, 1], [-1, 0]] (App. A); g2 = [[0, -i], [-i, 0]]
+    g[0][0] = mk<double2>(1, 0);
+    g[0][3] = mk<double2>(-1, 0);
+    g[1][1] = mk<double2>(1, 0);
+    g[1][2] = mk<double2>(-1, 0);
+    g[2][1] = mk<double2>(0, -1);
+    g[2][2] = mk<double2>(0, -1);
+    return;
+  }
+  // Dirac representation: g0 = diag(I, -I), gk = [[0, s_k], [-s_k, 0]]
+  for (int q = 0; q < 4; q++) g[0][q * 5] = mk<double2>(q < 2 ? 1 : -1, 0);
+  const double2 pauli[3][4] = {
+      {mk<double2>(0, 0), mk<double2>(1, 0), mk<double2>(1, 0), mk<double2>(0, 0)},
+      {mk<double2>(0, 0), mk<double2>(0, -1), mk<double2>(0, 1), mk<double2>(0, 0)},
+      {mk<double2>(1, 0), mk<double2>(0, 0), mk<double2>(0, 0), mk<double2>(-1, 0)}};
+  for (int k = 1; k <= 3; k++)
+    for (int a = 0; a < 2; a++)
+      for (int b = 0; b < 2; b++) {
+        double2 s = pauli[k - 1][a * 2 + b];
+        g[k][a * 4 + b + 2] = s;
+        g[k][(a + 2) * 4 + b] = mk<double2>(-s.x, -s.y);
+      }
+}
+
+static AsmParams make_params(const dirac_st_problem *p) {
+  AsmParams P{};
+  P.d = p->d;
+  P.nc = p->nc;
+  P.nt = p->n[0];
+  for (int a = 0; a < 4; a++) P.n[a] = (a <= p->d) ? p->n[a] : 1;
+  P.S = spatial_nodes(p);
+  P.nrows = P.S * P.nt;
+  P.nnzb = total_blocks(p);
+  int64_t st = 1;
+  P.stride[0] = 0;
+  for (int a = 1; a < 4; a++) {
+    P.stride[a] = st;
+    if (a <= p->d) st *= p->n[a];
+  }
+  for (int a = 0; a < 4; a++) {
+    double h = (a <= p->d) ? p->len[a] / p->n[a] : 1.0;
+    P.h[a] = h;
+    // closed forms of the 1D Q1 element integrals on [0, h]
+    P.M[a][0][0] = P.M[a][1][1] = h / 3.0;
+    P.M[a][0][1] = P.M[a][1][0] = h / 6.0;
+    P.Cd[a][0][0] = P.Cd[a][1][0] = -0.5;
+    P.Cd[a][0][1] = P.Cd[a][1][1] = 0.5;
+  }
+  P.m = p->m;
+  P.vkind = p->vkind;
+  P.v0 = p->v0;
+  P.x0 = p->x0;
+  P.lw = p->lw;
+  gamma_set(p->d, P.g);
+  P.sp3 = 1;
+  for (int a = 0; a < p->d; a++) P.sp3 *= 3;
+  P.c1 = blocks_per_row(p, 1);
+  P.cint = blocks_per_row(p, 2 <= P.nt - 1 ? 2 : 1);
+  P.clast = blocks_per_row(p, P.nt);
+  P.off_int = P.S * P.c1;
+  P.off_last = (P.nt >= 2) ? P.off_int + (int64_t)(P.nt - 2) * P.S * P.cint : P.off_int;
+  return P;
+}
+
+__device__ inline double potential(const AsmParams &P, double x) {
+  if (P.vkind == DIRAC_ST_V_STEP) return x > P.x0 ? P.v0 : 0.0;
+  if (P.vkind == DIRAC_ST_V_SMOOTH) return 0.5 * P.v0 * (1.0 + tanh((x - P.x0) / P.lw));
+  return 0.0;
+}
+
+// 2-point Gauss-Legendre: int_e V phi_b phi_a along axis 1, element e
+__device__ inline double potential_weight(const AsmParams &P, int e, int b, int a) {
+  const double h = P.h[1];
+  const double r3 = 0.57735026918962576451;  // 1/sqrt(3)
+  double acc = 0.0;
+  for (int q = 0; q < 2; q++) {
+    double xi = 0.5 * (1.0 + (q ? r3 : -r3));
+    double pb = b ? xi : 1.0 - xi, pa = a ? xi : 1.0 - xi;
+    acc += 0.5 * h * potential(P, (e + xi) * h) * pb * pa;
+  }
+  return acc;
+}
+
+// Block coupling the row node with coordinates gr (gr[0] = time node tau) to
+// the column node at offsets o (each -1, 0, +1).  blk: nc*nc entries.
+template <int NC>
+__device__ void block_value(const AsmParams &P, const int *gr, const int *o, double2 *blk) {
+  double KM[4], KC[4], KW = 0.0;
+  for (int a = 0; a <= P.d; a++) {
+    const int n = P.n[a];
+    int e[2], b[2], al[2], cnt = 0;
+    auto push = [&](int ee, int bb, int aa) {
+      if (a == 0) {
+        if (ee < 0 || ee >= n) return;
+      } else {
+        ee = (ee + n) % n;
+      }
+      e[cnt] = ee;
+      b[cnt] = bb;
+      al[cnt] = aa;
+      cnt++;
+    };
+    if (o[a] == 1) push(gr[a], 0, 1);
+    else if (o[a] == -1) push(gr[a] - 1, 1, 0);
+    else {
+      push(gr[a] - 1, 1, 1);
+      push(gr[a], 0, 0);
+    }
+    double km = 0.0, kc = 0.0, kw = 0.0;
+    for (int c = 0; c < cnt; c++) {
+      km += P.M[a][b[c]][al[c]];
+      kc += P.Cd[a][b[c]][al[c]];
+      if (a == 1 && P.vkind != DIRAC_ST_V_NONE) kw += potential_weight(P, e[c], b[c], al[c]);
+    }
+    KM[a] = km;
+    KC[a] = kc;
+    if (a == 1) KW = kw;
+  }
+  double Dmu[4], D0 = 1.0, Pw = KW;
+  for (int mu = 0; mu <= P.d; mu++) {
+    double v = 1.0;
+    for (int a = 0; a <= P.d; a++) v *= (a == mu) ? KC[a] : KM[a];
+    Dmu[mu] = v;
+  }
+  for (int a = 0; a <= P.d; a++) {
+    D0 *= KM[a];
+    if (a != 1) Pw *= KM[a];
+  }
+#pragma unroll
+  for (int i = 0; i < NC; i++)
+#pragma unroll
+    for (int j = 0; j < NC; j++) {
+      double re = 0.0, im = 0.0;
+      for (int mu = 0; mu <= P.d; mu++) {
+        double2 gg = P.g[mu][i * NC + j];
+        re -= gg.y * Dmu[mu];  // i * g
+        im += gg.x * Dmu[mu];
+      }
+      if (i == j) re -= P.m * D0;
+      double2 g0 = P.g[0][i * NC + j];
+      re -= g0.x * Pw;
+      im -= g0.y * Pw;
+      blk[i * NC + j] = mk<double2>(re, im);
+    }
+}
+
+// sorted neighbour offset of digit k along a periodic axis of length n (n >= 3)
+__device__ inline int spatial_offset(int i, int n, int k) {
+  if (i == 0) return k == 0 ? 0 : (k == 1 ? 1 : -1);
+  if (i == n - 1) return k == 0 ? 1 : (k == 1 ? -1 : 0);
+  return k - 1;
+}
+
+// Gauss-Jordan inverse with partial pivoting; returns false if singular or if
+// the 1-norm condition number exceeds 1e12.
+template <int NC>
+__device__ bool block_inverse(const double2 *a, double2 *inv) {
+  double2 m[NC][2 * NC];
+  double na = 0.0;
+  for (int j = 0; j < NC; j++) {
+    double s = 0.0;
+    for (int i = 0; i < NC; i++) s += sqrt(cabs2(a[i * NC + j]));
+    na = fmax(na, s);
+  }
+  for (int i = 0; i < NC; i++)
+    for (int j = 0; j < 2 * NC; j++)
+      m[i][j] = (j < NC) ? a[i * NC + j] : mk<double2>(j - NC == i ? 1.0 : 0.0, 0.0);
+  for (int c = 0; c < NC; c++) {
+    int piv = c;
+    for (int r = c + 1; r < NC; r++)
+      if (cabs2(m[r][c]) > cabs2(m[piv][c])) piv = r;
+    if (cabs2(m[piv][c]) == 0.0) return false;
+    for (int j = 0; j < 2 * NC; j++) {
+      double2 t = m[c][j];
+      m[c][j] = m[piv][j];
+      m[piv][j] = t;
+    }
+    double2 d = m[c][c];
+    double dd = 1.0 / cabs2(d);
+    double2 dinv = mk<double2>(d.x * dd, -d.y * dd);
+    for (int j = 0; j < 2 * NC; j++) m[c][j] = cmul(m[c][j], dinv);
+    for (int r = 0; r < NC; r++) {
+      if (r == c) continue;
+      double2 f = m[r][c];
+      for (int j = 0; j < 2 * NC; j++) m[r][j] = cfms(m[r][j], f, m[c][j]);
+    }
+  }
+  double ni = 0.0;
+  for (int j = 0; j < NC; j++) {
+    double s = 0.0;
+    for (int i = 0; i < NC; i++) s += sqrt(cabs2(m[i][NC + j]));
+    ni = fmax(ni, s);
+  }
+  for (int i = 0; i < NC; i++)
+    for (int j = 0; j < NC; j++) inv[i * NC + j] = m[i][NC + j];
+  return na * ni <= 1e12 && isfinite(na * ni);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void assemble_kernel(AsmParams P, int32_t *__restrict__ row_ptr,
+                                                        int32_t *__restrict__ col_idx,
+                                                        double2 *__restrict__ val64,
+                                                        float2 *__restrict__ val32,
+                                                        double2 *__restrict__ bj64,
+                                                        float2 *__restrict__ bj32,
+                                                        int32_t *__restrict__ nsingular) {
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kb >= P.nnzb) return;
+  int tau, k, c;
+  int64_t s;
+  if (kb < P.off_int) {
+    tau = 1;
+    c = P.c1;
+    s = kb / c;
+    k = (int)(kb - s * c);
+  } else if (kb < P.off_last) {
+    int64_t q = kb - P.off_int, per = P.S * P.cint;
+    int64_t sl = q / per;
+    tau = 2 + (int)sl;
+    q -= sl * per;
+    c = P.cint;
+    s = q / c;
+    k = (int)(q - s * c);
+  } else {
+    int64_t q = kb - P.off_last;
+    tau = P.nt;
+    c = P.clast;
+    s = q / c;
+    k = (int)(q - s * c);
+  }
+  const int64_t r = (int64_t)(tau - 1) * P.S + s;
+  int gr[4] = {tau, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+  int64_t ss = s;
+  for (int a = 1; a <= P.d; a++) {
+    gr[a] = (int)(ss % P.n[a]);
+    ss /= P.n[a];
+  }
+  // block position k -> offsets: time slowest, then axis d ... axis 1
+  int kt = k / P.sp3, ks = k - kt * P.sp3;
+  {
+    int list[3], nl = 0;
+    if (tau >= 2) list[nl++] = -1;
+    list[nl++] = 0;
+    if (tau <= P.nt - 1) list[nl++] = 1;
+    o[0] = list[kt];
+  }
+  int64_t colnode = (int64_t)(tau + o[0] - 1) * P.S;
+  bool diag = (o[0] == 0);
+  for (int a = 1; a <= P.d; a++) {
+    int dig = ks % 3;
+    ks /= 3;
+    o[a] = spatial_offset(gr[a], P.n[a], dig);
+    colnode += (int64_t)((gr[a] + o[a] + P.n[a]) % P.n[a]) * P.stride[a];
+    diag = diag && (o[a] == 0);
+  }
+  double2 blk[NC * NC];
+  block_value<NC>(P, gr, o, blk);
+  double2 *v64 = val64 + kb * NC * NC;
+#pragma unroll
+  for (int q = 0; q < NC * NC; q++) v64[q] = blk[q];
+  if (val32) {
+    float2 *v32 = val32 + kb * NC * NC;
+#pragma unroll
+    for (int q = 0; q < NC * NC; q++) v32[q] = to32(blk[q]);
+  }
+  col_idx[kb] = (int32_t)colnode;
+  if (k == 0) row_ptr[r] = (int32_t)kb;
+  if (kb == P.nnzb - 1) row_ptr[P.nrows] = (int32_t)P.nnzb;
+  if (diag && bj64) {
+    double2 inv[NC * NC];
+    if (!block_inverse<NC>(blk, inv)) {
+      atomicAdd(nsingular, 1);
+      for (int i = 0; i < NC; i++)
+        for (int j = 0; j < NC; j++) inv[i * NC + j] = mk<double2>(i == j ? 1.0 : 0.0, 0.0);
+    }
+    double2 *b64 = bj64 + r * NC * NC;
+    for (int q = 0; q < NC * NC; q++) b64[q] = inv[q];
+    if (bj32) {
+      float2 *b32 = bj32 + r * NC * NC;
+      for (int q = 0; q < NC * NC; q++) b32[q] = to32(inv[q]);
+    }
+  }
+}
+
+__global__ void zero_i32(int32_t *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// b = -D_w21 psi0: only rows of the first time slice see the t = 0 columns.
+template <int NC>
+__global__ __launch_bounds__(256) void rhs_kernel(AsmParams P, const double2 *__restrict__ psi0,
+                                                   double2 *__restrict__ b) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.nrows) return;
+  double2 acc[NC];
+  for (int i = 0; i < NC; i++) acc[i] = mk<double2>(0, 0);
+  if (r < P.S) {
+    int gr[4] = {1, 0, 0, 0}, o[4] = {-1, 0, 0, 0};
+    int64_t ss = r;
+    for (int a = 1; a <= P.d; a++) {
+      gr[a] = (int)(ss % P.n[a]);
+      ss /= P.n[a];
+    }
+    for (int ks = 0; ks < P.sp3; ks++) {
+      int t = ks;
+      int64_t col = 0;
+      for (int a = 1; a <= P.d; a++) {
+        o[a] = (t % 3) - 1;
+        t /= 3;
+        col += (int64_t)((gr[a] + o[a] + P.n[a]) % P.n[a]) * P.stride[a];
+      }
+      double2 blk[NC * NC];
+      block_value<NC>(P, gr, o, blk);
+      for (int i = 0; i < NC; i++)
+        for (int j = 0; j < NC; j++) acc[i] = cfma(acc[i], blk[i * NC + j], psi0[col * NC + j]);
+    }
+  }
+  for (int i = 0; i < NC; i++) b[r * NC + i] = mk<double2>(-acc[i].x, -acc[i].y);
+}
+
+}  // namespace dst
+
+using namespace dst;
+
+extern "C" int dirac_st_assemble(const dirac_st_problem *prob, const void *psi0, dirac_st_bsr *A,
+                                 void *b, void *stream) {
+  clear_error();
+  if (int rc = validate_problem(prob)) return rc;
+  DST_CHECK(A && A->row_ptr && A->col_idx && A->val64, "matrix arrays must be set");
+  DST_CHECK(!b || psi0, "psi0 is required to form b");
+  AsmParams P = make_params(prob);
+  DST_CHECK(A->nrows == P.nrows && A->nnzb == P.nnzb,
+            "A->nrows/nnzb (%lld/%lld) differ from dirac_st_sizes (%lld/%lld)",
+            (long long)A->nrows, (long long)A->nnzb, (long long)P.nrows, (long long)P.nnzb);
+  hipStream_t st = (hipStream_t)stream;
+  int32_t *dsing = nullptr;
+  if (A->bjinv64) {
+    DST_HIP(hipMallocAsync((void **)&dsing, sizeof(int32_t), st));
+    zero_i32<<<1, 64, 0, st>>>(dsing, 1);
+    DST_LAUNCHED();
+  }
+  const int bs = 256;
+  const unsigned grid = (unsigned)((P.nnzb + bs - 1) / bs);
+  if (P.nc == 2)
+    assemble_kernel<2><<<grid, bs, 0, st>>>(P, A->row_ptr, A->col_idx, (double2 *)A->val64,
+                                            (float2 *)A->val32, (double2 *)A->bjinv64,
+                                            (float2 *)A->bjinv32, dsing);
+  else
+    assemble_kernel<4><<<grid, bs, 0, st>>>(P, A->row_ptr, A->col_idx, (double2 *)A->val64,
+                                            (float2 *)A->val32, (double2 *)A->bjinv64,
+                                            (float2 *)A->bjinv32, dsing);
+  DST_LAUNCHED();
+  if (b) {
+    const unsigned g2 = (unsigned)((P.nrows + bs - 1) / bs);
+    if (P.nc == 2)
+      rhs_kernel<2><<<g2, bs, 0, st>>>(P, (const double2 *)psi0, (double2 *)b);
+    else
+      rhs_kernel<4><<<g2, bs, 0, st>>>(P, (const double2 *)psi0, (double2 *)b);
+    DST_LAUNCHED();
+  }
+  A->nc = prob->nc;
+  A->prob = *prob;
+  A->singular_blocks = 0;
+  if (dsing) {
+    int32_t h = 0;
+    DST_HIP(hipMemcpyAsync(&h, dsing, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    DST_HIP(hipFreeAsync(dsing, st));
+    DST_HIP(hipStreamSynchronize(st));
+    A->singular_blocks = h;
+  }
+  return DIRAC_ST_OK;
+}

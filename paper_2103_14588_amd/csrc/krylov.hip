@@ -1,0 +1,535 @@
+// krylov.hip -- restarted GMRES(m) with right preconditioning (Sec. 2.2 and
+// Alg. 1 step 6 of the paper), in complex128, or with complex64 inner cycles
+// inside an FP64 refinement loop; plus the SpMV and preconditioner entry
+// points of the C ABI.
+//
+// One cycle: r = b - A x in FP64 (val64); v_0 = r/||r||; for j = 0..m-1:
+// z = M^{-1} v_j, w = A z, two classical Gram-Schmidt passes against
+// v_0..v_j (the second pass re-orthogonalises), ||w||, a complex Givens
+// rotation on the new Hessenberg column; the cycle ends when the rotated
+// residual estimate meets the tolerance.  Then y solves the triangular
+// least-squares system and x += M^{-1} (V y).
+//
+// Device/host split: every vector operation is a kernel on `stream`; the
+// small FP64 state (Hessenberg column, rotations, g) stays on the device; the
+// host reads 32 bytes back after each Arnoldi step (residual estimate, happy
+// breakdown and NaN flags, next basis scale) to decide when to stop.
+// Basis vectors are stored unnormalised with a scale sigma_k kept in FP64,
+// so no separate normalisation pass is needed.
+#include <chrono>
+#include <cstring>
+
+#include "common.hpp"
+#include "krylov.hpp"
+#include "spectral.hpp"
+#include "spmv.hpp"
+
+namespace dst {
+
+// partial[0][b] = sum over the block's elements of |w[e]|^2
+template <typename T>
+__global__ __launch_bounds__(256) void norm_pass(const cx<T> *__restrict__ w,
+                                                  double2 *__restrict__ partial, int64_t n) {
+  __shared__ double red[4];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (e < n) {
+    cx<T> v = w[e];
+    s = (double)v.x * v.x + (double)v.y * v.y;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[blockIdx.x] = mk<double2>(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+
+__global__ __launch_bounds__(256) void zero_c128(double2 *x, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) x[e] = mk<double2>(0, 0);
+}
+
+static inline unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+static int maxk_bucket(int jp1) { return jp1 <= 8 ? 8 : jp1 <= 16 ? 16 : jp1 <= 32 ? 32 : 64; }
+
+template <typename T, int MODE>
+static hipError_t launch_pass_mk(int mk, const cx<T> *V, int64_t ldv, int jp1, cx<T> *w,
+                                 const double2 *coef, double2 *partial, int64_t n, hipStream_t s) {
+  const unsigned g = nblocks(n);
+  switch (mk) {
+    case 8: cgs_pass<T, 8, MODE><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    case 16: cgs_pass<T, 16, MODE><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    case 32: cgs_pass<T, 32, MODE><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    default: cgs_pass<T, 64, MODE><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+  }
+  return hipGetLastError();
+}
+
+// the fused update + dots pass keeps MAXK basis entries per lane in registers;
+// complex128 stops at 32 of them, larger Gram-Schmidt sets split the pass.
+template <typename T>
+static bool fused_updots_ok(int mk) {
+  return sizeof(T) == 4 ? mk <= 64 : mk <= 32;
+}
+
+template <typename T>
+static hipError_t launch_updots(int mk, const cx<T> *V, int64_t ldv, int jp1, cx<T> *w,
+                                const double2 *coef, double2 *partial, int64_t n, hipStream_t s) {
+  const unsigned g = nblocks(n);
+  switch (mk) {
+    case 8: cgs_pass<T, 8, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    case 16: cgs_pass<T, 16, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    case 32: cgs_pass<T, 32, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    default:
+      if constexpr (sizeof(T) == 4)
+        cgs_pass<T, 64, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ layout
+struct GmresLayout {
+  size_t V, z, u, r64, partial, ctrl, spec, total;
+  int64_t ldv;  // elements between basis vectors
+};
+
+static GmresLayout gmres_layout(const dirac_st_bsr *A, const dirac_st_opts *o) {
+  GmresLayout L{};
+  const int64_t N = A->nrows * A->nc;
+  const size_t cs = o->precision == 32 ? 8 : 16;
+  const size_t vb = align256((size_t)N * cs);
+  L.ldv = (int64_t)(vb / cs);
+  size_t off = 0;
+  L.V = off;
+  off += vb * (size_t)(o->restart + 1);
+  L.z = off;
+  off += vb;
+  L.u = off;
+  off += vb;
+  L.r64 = off;
+  if (o->precision == 32) off += align256((size_t)N * 16);
+  L.partial = off;
+  off += align256((size_t)nblocks(N) * kMaxRestart * sizeof(double2));
+  L.ctrl = off;
+  off += align256(sizeof(Ctrl));
+  L.spec = off;
+  if (o->pc == DIRAC_ST_PC_SPECTRAL) off += spec_layout(&A->prob, o->precision).total;
+  L.total = off;
+  return L;
+}
+
+// ------------------------------------------------------------ preconditioner
+struct Precond {
+  int kind = DIRAC_ST_PC_NONE;
+  int prec = 64;
+  const dirac_st_bsr *A = nullptr;
+  // spectral
+  SpecGeom G{};
+  unsigned char *spec = nullptr;
+  SpecLayout SL{};
+};
+
+static void spec_geom(const dirac_st_problem *p, double vbar, SpecGeom &G) {
+  G = SpecGeom{};
+  G.d = p->d;
+  G.nc = p->nc;
+  G.nt = p->n[0];
+  G.S = 1;
+  int64_t off = 0;
+  for (int a = 0; a < 4; a++) {
+    G.n[a] = (a <= p->d) ? p->n[a] : 1;
+    G.h[a] = (a <= p->d) ? p->len[a] / p->n[a] : 1.0;
+    G.tw_off[a] = 0;
+  }
+  for (int a = 1; a <= p->d; a++) {
+    G.S *= p->n[a];
+    G.tw_off[a] = off;
+    off += p->n[a];
+  }
+  G.m = p->m;
+  G.vbar = vbar;
+  for (int mu = 0; mu < 4; mu++)
+    for (int q = 0; q < 16; q++) G.g[mu][q] = mk<double2>(0, 0);
+  if (p->d <= 2) {
+    G.g[0][0] = mk<double2>(1, 0);
+    G.g[0][3] = mk<double2>(-1, 0);
+    G.g[1][1] = mk<double2>(1, 0);
+    G.g[1][2] = mk<double2>(-1, 0);
+    G.g[2][1] = mk<double2>(0, -1);
+    G.g[2][2] = mk<double2>(0, -1);
+  } else {
+    for (int q = 0; q < 4; q++) G.g[0][q * 5] = mk<double2>(q < 2 ? 1 : -1, 0);
+    const double2 P[3][4] = {
+        {mk<double2>(0, 0), mk<double2>(1, 0), mk<double2>(1, 0), mk<double2>(0, 0)},
+        {mk<double2>(0, 0), mk<double2>(0, -1), mk<double2>(0, 1), mk<double2>(0, 0)},
+        {mk<double2>(1, 0), mk<double2>(0, 0), mk<double2>(0, 0), mk<double2>(-1, 0)}};
+    for (int k = 1; k <= 3; k++)
+      for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+          double2 s = P[k - 1][a * 2 + b];
+          G.g[k][a * 4 + b + 2] = s;
+          G.g[k][(a + 2) * 4 + b] = mk<double2>(-s.x, -s.y);
+        }
+  }
+}
+
+// Twiddles exp(-2 pi i q / n_a) of every spatial axis, FP64 and FP32 copies.
+static int spec_twiddles(const SpecGeom &G, unsigned char *base, const SpecLayout &L, hipStream_t s) {
+  int64_t tot = 0;
+  for (int a = 1; a <= G.d; a++) tot += G.n[a];
+  double2 h64[3 * 4096];
+  float2 h32[3 * 4096];
+  DST_CHECK(tot <= 3 * 4096, "axis too long for the spectral preconditioner");
+  for (int a = 1; a <= G.d; a++)
+    for (int q = 0; q < G.n[a]; q++) {
+      const double th = 2.0 * M_PI * (double)q / (double)G.n[a];
+      h64[G.tw_off[a] + q] = mk<double2>(cos(th), -sin(th));
+      h32[G.tw_off[a] + q] = mk<float2>((float)cos(th), (float)-sin(th));
+    }
+  DST_HIP(hipMemcpyAsync(base + L.tw64, h64, tot * sizeof(double2), hipMemcpyHostToDevice, s));
+  DST_HIP(hipMemcpyAsync(base + L.tw32, h32, tot * sizeof(float2), hipMemcpyHostToDevice, s));
+  // the host arrays live on this stack frame: wait for the copies
+  DST_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+template <typename T>
+static int pc_setup(Precond &P, const dirac_st_bsr *A, int kind, double vbar, unsigned char *spec,
+                    hipStream_t s) {
+  P.kind = kind;
+  P.prec = sizeof(T) == 8 ? 64 : 32;
+  P.A = A;
+  if (kind == DIRAC_ST_PC_BLOCK_JACOBI) {
+    DST_CHECK((sizeof(T) == 8 ? A->bjinv64 : A->bjinv32) != nullptr,
+              "block-Jacobi preconditioner needs bjinv%d", P.prec);
+  }
+  if (kind != DIRAC_ST_PC_SPECTRAL) return 0;
+  P.spec = spec;
+  P.SL = spec_layout(&A->prob, P.prec);
+  spec_geom(&A->prob, vbar, P.G);
+  if (int rc = spec_twiddles(P.G, spec, P.SL, s)) return rc;
+  const unsigned g = (unsigned)((P.G.S + 63) / 64);
+  if (A->nc == 2)
+    spectral_setup<T, 2><<<g, 64, 0, s>>>(P.G, (const double2 *)(spec + P.SL.tw64), (cx<T> *)(spec + P.SL.piv));
+  else
+    spectral_setup<T, 4><<<g, 64, 0, s>>>(P.G, (const double2 *)(spec + P.SL.tw64), (cx<T> *)(spec + P.SL.piv));
+  DST_LAUNCHED();
+  return 0;
+}
+
+// z = scale * M^{-1} v  (v, z must differ)
+template <typename T>
+static int pc_apply(const Precond &P, const cx<T> *v, cx<T> *z, double scale, int64_t N,
+                    hipStream_t s) {
+  const dirac_st_bsr *A = P.A;
+  if (P.kind == DIRAC_ST_PC_BLOCK_JACOBI) {
+    const cx<T> *binv = (const cx<T> *)(sizeof(T) == 8 ? A->bjinv64 : A->bjinv32);
+    if (A->nc == 2)
+      block_jacobi_apply<T, 2><<<nblocks(N), 256, 0, s>>>(binv, v, (T)scale, z, A->nrows);
+    else
+      block_jacobi_apply<T, 4><<<nblocks(N), 256, 0, s>>>(binv, v, (T)scale, z, A->nrows);
+    DST_LAUNCHED();
+    return 0;
+  }
+  if (P.kind == DIRAC_ST_PC_SPECTRAL) {
+    const SpecGeom &G = P.G;
+    const cx<T> *tw = (const cx<T> *)(P.spec + (sizeof(T) == 8 ? P.SL.tw64 : P.SL.tw32));
+    const int nc = G.nc;
+    int64_t stride = nc;
+    const int64_t total = G.S * G.nt * nc;
+    // forward transforms, axis 1 first (v -> z), then in place
+    for (int pass = 0; pass < 2; pass++) {
+      stride = nc;
+      for (int a = 1; a <= G.d; a++) {
+        const int n = G.n[a];
+        const int64_t outer = total / ((int64_t)n * stride);
+        int ti = (int)(stride < 2048 / n ? stride : 2048 / n);
+        if (ti < 1) ti = 1;
+        while (stride % ti) ti--;
+        const int ntq = (int)(stride / ti);
+        const size_t sh = ((size_t)n * ti + n) * sizeof(cx<T>);
+        const bool first = (pass == 0 && a == 1);
+        const bool last = (pass == 1 && a == G.d);
+        const T sc = last ? (T)(scale / (double)G.S) : (T)1;
+        dft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(first ? v : z, z, n, stride, ti, ntq,
+                                                            pass == 0 ? -1 : 1, sc,
+                                                            tw + G.tw_off[a]);
+        DST_LAUNCHED();
+        stride *= n;
+      }
+      if (pass == 0) {
+        const unsigned g = (unsigned)((G.S + 63) / 64);
+        const double2 *tw64 = (const double2 *)(P.spec + P.SL.tw64);
+        const cx<T> *piv = (const cx<T> *)(P.spec + P.SL.piv);
+        if (nc == 2)
+          spectral_thomas<T, 2><<<g, 64, 0, s>>>(G, tw64, piv, z);
+        else
+          spectral_thomas<T, 4><<<g, 64, 0, s>>>(G, tw64, piv, z);
+        DST_LAUNCHED();
+      }
+    }
+    return 0;
+  }
+  set_error("no preconditioner to apply");
+  return DIRAC_ST_EINVAL;
+}
+
+// ------------------------------------------------------------ GMRES
+struct Readback {
+  double est_abs, happy, finite, sigma_next;
+};
+
+template <typename T>
+static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const dirac_st_opts *o,
+                      unsigned char *work, dirac_st_stats *st, hipStream_t s) {
+  using C = cx<T>;
+  const auto t_start = std::chrono::steady_clock::now();
+  const int nc = A->nc;
+  const int64_t N = A->nrows * nc;
+  const int m = o->restart;
+  const GmresLayout L = gmres_layout(A, o);
+  C *V = (C *)(work + L.V);
+  C *z = (C *)(work + L.z);
+  C *u = (C *)(work + L.u);
+  double2 *r64 = (double2 *)(work + L.r64);
+  double2 *partial = (double2 *)(work + L.partial);
+  Ctrl *ctrl = (Ctrl *)(work + L.ctrl);
+  const int64_t nblk = nblocks(N);
+  const void *val = sizeof(T) == 8 ? A->val64 : A->val32;
+
+  Precond P;
+  if (int rc = pc_setup<T>(P, A, o->pc, o->vbar, work + L.spec, s)) return rc;
+  zero_ctrl<<<8, 256, 0, s>>>(ctrl);
+  DST_LAUNCHED();
+
+  auto read_norm = [&](const double2 *v, double &out) -> int {
+    norm_pass<double><<<nblocks(N), 256, 0, s>>>(v, partial, N);
+    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
+    DST_LAUNCHED();
+    DST_HIP(hipMemcpyAsync(&out, &ctrl->dots_norm2, sizeof(double), hipMemcpyDeviceToHost, s));
+    DST_HIP(hipStreamSynchronize(s));
+    out = sqrt(out);
+    return 0;
+  };
+
+  dirac_st_stats local{};
+  dirac_st_stats &S = st ? *st : local;
+  double *hist = st ? st->history : nullptr;
+  const int hist_len = st ? st->history_len : 0;
+  S.iters = S.cycles = S.converged = 0;
+  S.singular_blocks = A->singular_blocks;
+  S.relres = S.est = 0.0;
+
+  double bnorm = 0.0;
+  if (int rc = read_norm(b, bnorm)) return rc;
+  if (!std::isfinite(bnorm)) {
+    set_error("right-hand side contains NaN or Inf");
+    return DIRAC_ST_EBREAKDOWN;
+  }
+  if (bnorm == 0.0) {
+    zero_c128<<<nblocks(N), 256, 0, s>>>(x, N);
+    DST_LAUNCHED();
+    DST_HIP(hipStreamSynchronize(s));
+    S.converged = 1;
+    return DIRAC_ST_OK;
+  }
+  int its = 0, rc_final = DIRAC_ST_NOT_CONVERGED;
+  double2 *rbuf = sizeof(T) == 8 ? (double2 *)V : r64;
+  for (;;) {
+    // true residual in FP64
+    DST_HIP(launch_spmv<double>(nc, A->nrows, A->row_ptr, A->col_idx, A->val64, x, b, rbuf, 1.0,
+                                true, s));
+    double rn = 0.0;
+    if (int rc = read_norm(rbuf, rn)) return rc;
+    S.relres = rn / bnorm;
+    if (!std::isfinite(rn)) {
+      set_error("NaN or Inf in the residual");
+      rc_final = DIRAC_ST_EBREAKDOWN;
+      break;
+    }
+    if (S.relres <= o->rtol) {
+      S.converged = 1;
+      rc_final = DIRAC_ST_OK;
+      break;
+    }
+    if (its >= o->max_it || (o->max_cycles > 0 && S.cycles >= o->max_cycles)) break;
+    S.cycles++;
+    if (sizeof(T) == 8) {
+      cycle_init<<<1, 64, 0, s>>>(ctrl, rn, 1.0 / rn);
+    } else {
+      scale_convert<T><<<nblocks(N), 256, 0, s>>>(r64, 1.0 / rn, V, N);
+      cycle_init<<<1, 64, 0, s>>>(ctrl, rn, 1.0);
+    }
+    DST_LAUNCHED();
+    double sigma_j = sizeof(T) == 8 ? 1.0 / rn : 1.0;
+    int k = 0;
+    bool broke = false;
+    for (int j = 0; j < m && its < o->max_it; j++) {
+      C *vj = V + (int64_t)j * L.ldv;
+      C *w = V + (int64_t)(j + 1) * L.ldv;
+      // w = A M^{-1} v_j
+      if (P.kind == DIRAC_ST_PC_NONE) {
+        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, vj, nullptr, w,
+                               (T)sigma_j, false, s));
+      } else {
+        if (int rc = pc_apply<T>(P, vj, z, sigma_j, N, s)) return rc;
+        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, z, nullptr, w, (T)1,
+                               false, s));
+      }
+      const int jp1 = j + 1, mk = maxk_bucket(jp1);
+      // pass 1: h1 = V^H w
+      DST_HIP((launch_pass_mk<T, DOTS>(mk, V, L.ldv, jp1, w, nullptr, partial, N, s)));
+      reduce_partials<<<jp1, 256, 0, s>>>(partial, nblk, ctrl, 0, 1);
+      DST_LAUNCHED();
+      // pass 2: w -= V h1, h2 = V^H w
+      if (fused_updots_ok<T>(mk)) {
+        DST_HIP(launch_updots<T>(mk, V, L.ldv, jp1, w, ctrl->coef, partial, N, s));
+      } else {
+        DST_HIP((launch_pass_mk<T, UPDATE>(mk, V, L.ldv, jp1, w, ctrl->coef, partial, N, s)));
+        DST_HIP((launch_pass_mk<T, DOTS>(mk, V, L.ldv, jp1, w, nullptr, partial, N, s)));
+      }
+      reduce_partials<<<jp1, 256, 0, s>>>(partial, nblk, ctrl, 0, 2);
+      DST_LAUNCHED();
+      // pass 3: w -= V h2, ||w||^2
+      DST_HIP((launch_pass_mk<T, UPNORM>(mk, V, L.ldv, jp1, w, ctrl->coef, partial, N, s)));
+      reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
+      givens_step<<<1, 64, 0, s>>>(ctrl, j);
+      DST_LAUNCHED();
+      Readback rb{};
+      DST_HIP(hipMemcpyAsync(&rb, &ctrl->est_abs, sizeof(rb), hipMemcpyDeviceToHost, s));
+      DST_HIP(hipStreamSynchronize(s));
+      its++;
+      k = j + 1;
+      const double est = rb.est_abs / bnorm;
+      S.est = est;
+      if (hist && its <= hist_len) hist[its - 1] = est;
+      if (rb.finite == 0.0 || !std::isfinite(est)) {
+        broke = true;
+        break;
+      }
+      sigma_j = rb.sigma_next;
+      if (est <= o->rtol || rb.happy != 0.0) break;
+      if (sizeof(T) == 4 && o->inner_rtol > 0.0 && rb.est_abs <= o->inner_rtol * rn) break;
+    }
+    if (broke) {
+      set_error("NaN or Inf in the Arnoldi process");
+      rc_final = DIRAC_ST_EBREAKDOWN;
+      break;
+    }
+    // x += M^{-1} V y
+    back_substitute<<<1, 64, 0, s>>>(ctrl, k);
+    DST_LAUNCHED();
+    if (P.kind == DIRAC_ST_PC_NONE) {
+      combine<T, double, true><<<nblocks(N), 256, 0, s>>>(V, L.ldv, k, ctrl->coef, x, N);
+      DST_LAUNCHED();
+    } else {
+      combine<T, T, false><<<nblocks(N), 256, 0, s>>>(V, L.ldv, k, ctrl->coef, u, N);
+      DST_LAUNCHED();
+      if (int rc = pc_apply<T>(P, u, z, 1.0, N, s)) return rc;
+      add_into64<T><<<nblocks(N), 256, 0, s>>>(x, z, N);
+      DST_LAUNCHED();
+    }
+  }
+  S.iters = its;
+  DST_HIP(hipStreamSynchronize(s));
+  S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return rc_final;
+}
+
+static int check_bsr(const dirac_st_bsr *A) {
+  DST_CHECK(A != nullptr, "matrix is NULL");
+  DST_CHECK(A->row_ptr && A->col_idx && A->val64, "matrix arrays are NULL");
+  DST_CHECK(A->nc == 2 || A->nc == 4, "matrix nc must be 2 or 4 (was it assembled?)");
+  DST_CHECK(A->nrows > 0 && A->nnzb > 0, "empty matrix");
+  return 0;
+}
+
+}  // namespace dst
+
+using namespace dst;
+
+extern "C" int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x, void *y,
+                             void *stream) {
+  clear_error();
+  if (int rc = check_bsr(A)) return rc;
+  DST_CHECK(prec == 64 || prec == 32, "prec must be 64 or 32");
+  DST_CHECK(x && y, "x and y must be set");
+  DST_CHECK(x != y, "x and y must not overlap");
+  DST_CHECK(prec == 64 || A->val32, "prec 32 needs val32");
+  DST_CHECK(((uintptr_t)x & 15) == 0 && ((uintptr_t)y & 15) == 0, "x, y must be 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == 64)
+    DST_HIP(launch_spmv<double>(A->nc, A->nrows, A->row_ptr, A->col_idx, A->val64, x, nullptr, y,
+                                1.0, false, s));
+  else
+    DST_HIP(launch_spmv<float>(A->nc, A->nrows, A->row_ptr, A->col_idx, A->val32, x, nullptr, y,
+                               1.0f, false, s));
+  return DIRAC_ST_OK;
+}
+
+extern "C" size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *o,
+                                           int32_t flexible) {
+  if (!A || !o || (A->nc != 2 && A->nc != 4)) return 0;
+  (void)flexible;
+  dirac_st_opts oo = *o;
+  if (oo.restart < 1) oo.restart = 1;
+  if (oo.restart > kMaxRestart) oo.restart = kMaxRestart;
+  return gmres_layout(A, &oo).total;
+}
+
+extern "C" int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec, double vbar,
+                                 const void *v, void *z, void *work, size_t work_bytes,
+                                 void *stream) {
+  clear_error();
+  if (int rc = check_bsr(A)) return rc;
+  DST_CHECK(prec == 64 || prec == 32, "prec must be 64 or 32");
+  DST_CHECK(pc == DIRAC_ST_PC_BLOCK_JACOBI || pc == DIRAC_ST_PC_SPECTRAL, "pc must be 1 or 2");
+  DST_CHECK(v && z && v != z, "v and z must be set and distinct");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = A->nrows * A->nc;
+  if (pc == DIRAC_ST_PC_SPECTRAL) {
+    const size_t need = spec_layout(&A->prob, prec).total;
+    DST_CHECK(work != nullptr, "spectral preconditioner needs a workspace");
+    if (work_bytes < need) {
+      set_error("workspace too small: %zu < %zu", work_bytes, need);
+      return DIRAC_ST_ENOSPACE;
+    }
+  }
+  Precond P;
+  if (prec == 64) {
+    if (int rc = pc_setup<double>(P, A, pc, vbar, (unsigned char *)work, s)) return rc;
+    return pc_apply<double>(P, (const double2 *)v, (double2 *)z, 1.0, N, s);
+  }
+  if (int rc = pc_setup<float>(P, A, pc, vbar, (unsigned char *)work, s)) return rc;
+  return pc_apply<float>(P, (const float2 *)v, (float2 *)z, 1.0, N, s);
+}
+
+extern "C" int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x,
+                              const dirac_st_opts *opts, void *work, size_t work_bytes,
+                              dirac_st_stats *stats, void *stream) {
+  clear_error();
+  if (int rc = check_bsr(A)) return rc;
+  DST_CHECK(opts != nullptr, "opts is NULL");
+  DST_CHECK(b && x && work, "b, x and work must be set");
+  DST_CHECK(opts->restart >= 1 && opts->restart <= kMaxRestart, "restart must be in 1..%d",
+            kMaxRestart);
+  DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
+  DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
+  DST_CHECK(opts->pc >= 0 && opts->pc <= 2, "unknown preconditioner %d", opts->pc);
+  DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
+  DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
+  const size_t need = gmres_layout(A, opts).total;
+  if (work_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", work_bytes, need);
+    return DIRAC_ST_ENOSPACE;
+  }
+  DST_CHECK(((uintptr_t)work & 255) == 0, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (opts->precision == 64)
+    return gmres_impl<double>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work,
+                              stats, s);
+  return gmres_impl<float>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work, stats,
+                           s);
+}

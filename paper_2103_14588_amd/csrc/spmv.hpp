@@ -1,0 +1,112 @@
+// spmv.hpp -- block-CSR SpMV kernels (y = alpha A x and r = b - A x).
+//
+// The product inside GMRES (Sec. 2.2).  Work split: G consecutive lanes own
+// one block row.  The row's values are contiguous ([nnzb][nc][nc]), so the
+// group walks them in 16-byte chunks: lane l always reads chunk l of each
+// G-chunk slice, which keeps the wavefront's loads fully coalesced and fixes
+// the output component i of every lane.  A chunk is one complex128 entry, or
+// two adjacent complex64 entries of the same block row (16 bytes either way);
+// the x operand of a chunk is the matching 16 bytes of the column node.
+// Values are streamed with nontemporal loads so that x stays in cache.
+// Partial sums are combined with xor shuffles over the lane bits that do not
+// encode i.  Tiles of rows are assigned so that each XCD gets a contiguous
+// share of rows (x reuse in that XCD's L2).
+#pragma once
+
+#include "common.hpp"
+
+namespace dst {
+
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+// 16-byte chunk: one complex128 or two complex64 values (clang vector types,
+// so the nontemporal load builtin accepts them)
+template <typename T> struct chunk_of;
+template <> struct chunk_of<double> { using type = dv2; static constexpr int J = 1; };
+template <> struct chunk_of<float> { using type = fv4; static constexpr int J = 2; };
+
+template <typename T>
+__device__ inline cx<T> chunk_mac(cx<T> acc, typename chunk_of<T>::type v, typename chunk_of<T>::type x);
+template <>
+__device__ inline double2 chunk_mac<double>(double2 acc, dv2 v, dv2 x) {
+  return cfma(acc, mk<double2>(v.x, v.y), mk<double2>(x.x, x.y));
+}
+template <>
+__device__ inline float2 chunk_mac<float>(float2 acc, fv4 v, fv4 x) {
+  acc = cfma(acc, mk<float2>(v.x, v.y), mk<float2>(x.x, x.y));
+  return cfma(acc, mk<float2>(v.z, v.w), mk<float2>(x.z, x.w));
+}
+
+template <typename T, int NC, int G, bool RESID>
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, int64_t nwg,
+                                                   const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const cx<T> *__restrict__ val,
+                                                   const cx<T> *__restrict__ x,
+                                                   const cx<T> *__restrict__ bvec,
+                                                   cx<T> *__restrict__ y, T alpha) {
+  using Ch = typename chunk_of<T>::type;
+  constexpr int J = chunk_of<T>::J;
+  constexpr int IB = NC / J;          // chunks per block row
+  constexpr int CPB = NC * NC / J;    // chunks per block
+  constexpr int BPI = G / CPB;        // blocks per group slice
+  constexpr int RPW = 256 / G;        // rows per workgroup
+  constexpr int IMASK = (NC - 1) * IB;
+  static_assert(G % CPB == 0 && G <= 64, "group must hold whole blocks");
+  const int64_t tile = xcd_tile(blockIdx.x, nwg);
+  const int lane = threadIdx.x % G;
+  const int64_t row = tile * RPW + threadIdx.x / G;
+  const int i = (lane / IB) % NC;
+  const int jc = lane % IB;
+  const int bofs = lane / CPB;
+  cx<T> acc = mk<cx<T>>(0, 0);
+  if (row < nrows) {
+    const int rs = rp[row], re = rp[row + 1];
+    const Ch *vbase = reinterpret_cast<const Ch *>(val + i * NC + jc * J);
+    for (int b = rs + bofs; b < re; b += BPI) {
+      Ch v = __builtin_nontemporal_load(vbase + (int64_t)b * (NC * NC / J));
+      const int c = ci[b];
+      Ch xv = *reinterpret_cast<const Ch *>(x + (int64_t)c * NC + jc * J);
+      acc = chunk_mac<T>(acc, v, xv);
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    if (off & IMASK) continue;
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+  }
+  if (row < nrows && lane == i * IB) {
+    const int64_t o = row * NC + i;
+    if (RESID) {
+      cx<T> bb = bvec[o];
+      y[o] = mk<cx<T>>(bb.x - acc.x, bb.y - acc.y);
+    } else {
+      y[o] = mk<cx<T>>(alpha * acc.x, alpha * acc.y);
+    }
+  }
+}
+
+// Host launcher: picks the group size for (T, nc).  resid: y = bvec - A x.
+template <typename T>
+inline hipError_t launch_spmv(int nc, int64_t nrows, const int32_t *rp, const int32_t *ci,
+                              const void *val, const void *x, const void *bvec, void *y, T alpha,
+                              bool resid, hipStream_t st) {
+  auto go = [&](auto kern, int G) {
+    const int64_t rpw = 256 / G;
+    const int64_t nwg = (nrows + rpw - 1) / rpw;
+    kern<<<(unsigned)nwg, 256, 0, st>>>(nrows, nwg, rp, ci, (const cx<T> *)val, (const cx<T> *)x,
+                                        (const cx<T> *)bvec, (cx<T> *)y, alpha);
+    return hipGetLastError();
+  };
+  constexpr bool dbl = sizeof(T) == 8;
+  if (nc == 2) {
+    constexpr int G = dbl ? 16 : 8;
+    return resid ? go(spmv_kernel<T, 2, G, true>, G) : go(spmv_kernel<T, 2, G, false>, G);
+  }
+  constexpr int G4 = dbl ? 64 : 32;
+  return resid ? go(spmv_kernel<T, 4, G4, true>, G4) : go(spmv_kernel<T, 4, G4, false>, G4);
+}
+
+}  // namespace dst

@@ -1,0 +1,237 @@
+"""Python binding of the C ABI in include/dirac_st.h (ctypes).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the solve runs in libdirac_st.so.  Importing
+this module fails loudly if the library has not been built
+(``python -m paper_2103_14588_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdirac_st.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdirac_st.so is not built; run `python -m paper_2103_14588_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+OK, NOT_CONVERGED, EINVAL, EHIP, EBREAKDOWN, ENOSPACE = 0, 1, -1, -2, -3, -4
+V_NONE, V_STEP, V_SMOOTH = 0, 1, 2
+PC_NONE, PC_BLOCK_JACOBI, PC_SPECTRAL = 0, 1, 2
+PC_NAMES = {"none": PC_NONE, "bj": PC_BLOCK_JACOBI, "spectral": PC_SPECTRAL}
+
+
+class Problem(C.Structure):
+    _fields_ = [("d", C.c_int32), ("nc", C.c_int32), ("n", C.c_int32 * 4), ("len", C.c_double * 4),
+                ("m", C.c_double), ("vkind", C.c_int32), ("v0", C.c_double), ("x0", C.c_double),
+                ("lw", C.c_double)]
+
+
+class BSR(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val64", C.c_void_p),
+                ("val32", C.c_void_p), ("bjinv64", C.c_void_p), ("bjinv32", C.c_void_p),
+                ("nrows", C.c_int64), ("nnzb", C.c_int64), ("nc", C.c_int32),
+                ("singular_blocks", C.c_int32), ("prob", Problem)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("pc", C.c_int32),
+                ("precision", C.c_int32), ("max_cycles", C.c_int32), ("rtol", C.c_double),
+                ("inner_rtol", C.c_double), ("vbar", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("cycles", C.c_int32), ("converged", C.c_int32),
+                ("singular_blocks", C.c_int32), ("relres", C.c_double), ("est", C.c_double),
+                ("ms", C.c_double), ("history", C.POINTER(C.c_double)), ("history_len", C.c_int32)]
+
+
+_vp, _i32, _i64 = C.c_void_p, C.c_int32, C.c_int64
+_lib.dirac_st_last_error.restype = C.c_char_p
+_lib.dirac_st_sizes.argtypes = [C.POINTER(Problem), C.POINTER(_i64), C.POINTER(_i64)]
+_lib.dirac_st_assemble.argtypes = [C.POINTER(Problem), _vp, C.POINTER(BSR), _vp, _vp]
+_lib.dirac_st_spmv.argtypes = [C.POINTER(BSR), _i32, _vp, _vp, _vp]
+_lib.dirac_st_pc_apply.argtypes = [C.POINTER(BSR), _i32, _i32, C.c_double, _vp, _vp, _vp, C.c_size_t, _vp]
+_lib.dirac_st_workspace_bytes.argtypes = [C.POINTER(BSR), C.POINTER(Opts), _i32]
+_lib.dirac_st_workspace_bytes.restype = C.c_size_t
+_lib.dirac_st_gmres.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, C.c_size_t,
+                                C.POINTER(Stats), _vp]
+
+EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_st_spmv",
+           "dirac_st_pc_apply", "dirac_st_workspace_bytes", "dirac_st_gmres"]
+
+
+class DiracError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("dirac_st error %d: %s" % (code, msg))
+        self.code = code
+
+
+def last_error() -> str:
+    return _lib.dirac_st_last_error().decode()
+
+
+def _check(rc, allow=(OK,)):
+    if rc not in allow:
+        raise DiracError(rc, last_error())
+    return rc
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def make_problem(spec) -> Problem:
+    """From paper_2103_14588_amd.inputs.Spec (or any object with the same fields)."""
+    p = Problem()
+    p.d, p.nc = spec.d, spec.nc
+    for a in range(4):
+        p.n[a] = spec.n[a] if a <= spec.d else 1
+        p.len[a] = spec.lens[a] if a <= spec.d else 1.0
+    p.m, p.vkind, p.v0, p.x0, p.lw = spec.m, spec.vkind, spec.v0, spec.x0, spec.lw
+    return p
+
+
+def sizes(spec):
+    p = make_problem(spec)
+    nr, nb = _i64(), _i64()
+    _check(_lib.dirac_st_sizes(C.byref(p), C.byref(nr), C.byref(nb)))
+    return nr.value, nb.value
+
+
+@dataclass
+class Operator:
+    """Assembled operator; owns its device tensors."""
+    spec: object
+    bsr: BSR
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val64: torch.Tensor
+    val32: torch.Tensor | None
+    bjinv64: torch.Tensor | None
+    bjinv32: torch.Tensor | None
+
+    @property
+    def nrows(self):
+        return self.bsr.nrows
+
+    @property
+    def nnzb(self):
+        return self.bsr.nnzb
+
+    @property
+    def nc(self):
+        return self.bsr.nc
+
+    @property
+    def n(self):
+        return self.bsr.nrows * self.bsr.nc
+
+    def bytes(self):
+        return sum(t.numel() * t.element_size() for t in
+                   (self.row_ptr, self.col_idx, self.val64, self.val32, self.bjinv64, self.bjinv32)
+                   if t is not None)
+
+
+def assemble(spec, psi0: torch.Tensor | None, fp32: bool = True, block_jacobi: bool = True,
+             device="cuda"):
+    """dirac_st_assemble: returns (Operator, b).  psi0: complex128 [S*nc] on device."""
+    nrows, nnzb = sizes(spec)
+    nc = spec.nc
+    dev = torch.device(device)
+    rp = torch.empty(nrows + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(nnzb, dtype=torch.int32, device=dev)
+    v64 = torch.empty(nnzb * nc * nc, dtype=torch.complex128, device=dev)
+    v32 = torch.empty(nnzb * nc * nc, dtype=torch.complex64, device=dev) if fp32 else None
+    bj64 = torch.empty(nrows * nc * nc, dtype=torch.complex128, device=dev) if block_jacobi else None
+    bj32 = torch.empty(nrows * nc * nc, dtype=torch.complex64, device=dev) if (block_jacobi and fp32) else None
+    A = BSR()
+    A.row_ptr, A.col_idx, A.val64 = rp.data_ptr(), ci.data_ptr(), v64.data_ptr()
+    A.val32 = v32.data_ptr() if v32 is not None else None
+    A.bjinv64 = bj64.data_ptr() if bj64 is not None else None
+    A.bjinv32 = bj32.data_ptr() if bj32 is not None else None
+    A.nrows, A.nnzb = nrows, nnzb
+    b = None
+    if psi0 is not None:
+        assert psi0.dtype == torch.complex128 and psi0.is_contiguous() and psi0.numel() == spec.spatial * nc
+        b = torch.empty(nrows * nc, dtype=torch.complex128, device=dev)
+    p = make_problem(spec)
+    _check(_lib.dirac_st_assemble(C.byref(p), _ptr(psi0), C.byref(A), _ptr(b), _stream()))
+    return Operator(spec, A, rp, ci, v64, v32, bj64, bj32), b
+
+
+def assemble_into(op: Operator, psi0: torch.Tensor | None, b: torch.Tensor | None) -> None:
+    """dirac_st_assemble into the arrays of an existing Operator (same mesh)."""
+    p = make_problem(op.spec)
+    _check(_lib.dirac_st_assemble(C.byref(p), _ptr(psi0), C.byref(op.bsr), _ptr(b), _stream()))
+
+
+def spmv(op: Operator, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    """dirac_st_spmv in the precision of x (complex128 -> 64, complex64 -> 32)."""
+    prec = 64 if x.dtype == torch.complex128 else 32
+    if y is None:
+        y = torch.empty_like(x)
+    _check(_lib.dirac_st_spmv(C.byref(op.bsr), prec, _ptr(x), _ptr(y), _stream()))
+    return y
+
+
+def pc_apply(op: Operator, v: torch.Tensor, pc="spectral", vbar=0.0, z=None, work=None):
+    prec = 64 if v.dtype == torch.complex128 else 32
+    kind = PC_NAMES[pc] if isinstance(pc, str) else pc
+    if z is None:
+        z = torch.empty_like(v)
+    o = Opts(restart=1, max_it=1, pc=kind, precision=prec, max_cycles=0, rtol=1e-8, inner_rtol=0.0,
+             vbar=vbar)
+    nbytes = 0
+    if kind == PC_SPECTRAL:
+        nbytes = _lib.dirac_st_workspace_bytes(C.byref(op.bsr), C.byref(o), 0)
+        if work is None or work.numel() < nbytes:
+            work = torch.empty(nbytes, dtype=torch.uint8, device=v.device)
+    _check(_lib.dirac_st_pc_apply(C.byref(op.bsr), kind, prec, vbar, _ptr(v), _ptr(z), _ptr(work),
+                                  work.numel() if work is not None else 0, _stream()))
+    return z
+
+
+def make_opts(restart=50, max_it=20000, pc="bj", precision=64, max_cycles=0, rtol=1e-8,
+              inner_rtol=0.0, vbar=0.0) -> Opts:
+    return Opts(restart=restart, max_it=max_it, pc=PC_NAMES[pc] if isinstance(pc, str) else pc,
+                precision=precision, max_cycles=max_cycles, rtol=rtol, inner_rtol=inner_rtol,
+                vbar=vbar)
+
+
+def workspace_bytes(op: Operator, opts: Opts, flexible=False) -> int:
+    return int(_lib.dirac_st_workspace_bytes(C.byref(op.bsr), C.byref(opts), 1 if flexible else 0))
+
+
+def gmres(op: Operator, b: torch.Tensor, x: torch.Tensor | None = None, opts: Opts | None = None,
+          work: torch.Tensor | None = None, history: int = 0, **kw):
+    """dirac_st_gmres.  Returns (x, stats dict).  kw build the options when opts is None."""
+    if opts is None:
+        opts = make_opts(**kw)
+    if x is None:
+        x = torch.zeros_like(b)
+    nbytes = workspace_bytes(op, opts)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    st = Stats()
+    hist = None
+    if history:
+        hist = (C.c_double * history)()
+        st.history = C.cast(hist, C.POINTER(C.c_double))
+        st.history_len = history
+    rc = _lib.dirac_st_gmres(C.byref(op.bsr), _ptr(b), _ptr(x), C.byref(opts), _ptr(work),
+                             work.numel(), C.byref(st), _stream())
+    _check(rc, allow=(OK, NOT_CONVERGED))
+    info = dict(rc=rc, iters=st.iters, cycles=st.cycles, converged=bool(st.converged),
+                relres=st.relres, est=st.est, ms=st.ms, singular_blocks=st.singular_blocks)
+    if hist is not None:
+        info["history"] = [hist[i] for i in range(min(st.iters, history))]
+    return x, info

@@ -1,0 +1,62 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and the host-only size query agrees with the oracle and
+rejects invalid problems.  No GPU work is launched here."""
+import os
+import re
+
+import pytest
+
+from oracle import oracle as O
+from paper_2103_14588_amd import inputs as IN
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "dirac_st.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dirac_st_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2103_14588_amd import dirac_st as D
+    names = declared_functions()
+    assert len(names) >= 7
+    for n in names:
+        assert hasattr(D._lib, n), n
+    assert set(D.EXPORTS) <= set(names)
+
+
+@pytest.mark.parametrize("spec", [
+    IN.Spec(d=1, n=[64, 64]), IN.Spec(d=1, n=[1, 3]), IN.Spec(d=1, n=[2, 5]),
+    IN.Spec(d=2, n=[7, 5, 3]), IN.Spec(d=2, n=[128, 128, 128]),
+    IN.Spec(d=3, n=[12, 12, 12, 12]), IN.Spec(d=3, n=[32, 32, 32, 32]),
+])
+def test_sizes_match_oracle(spec):
+    from paper_2103_14588_amd import dirac_st as D
+    nrows, nnzb = D.sizes(spec)
+    assert nrows == spec.nrows
+    p = O.problem(spec.d, spec.n, spec.lens)
+    assert nrows == O.nrows(p)
+    if spec.nunknowns < 200000:
+        assert nnzb == O.Matrix(p).export()[1].shape[0]
+    # closed forms quoted for the large configurations
+    if spec.n == [128, 128, 128]:
+        assert (nrows, nnzb) == (2097152, 56328192)
+    if spec.n == [32] * 4:
+        assert (nrows, nnzb) == (1048576, 83165184)
+
+
+@pytest.mark.parametrize("bad", [
+    IN.Spec(d=4, n=[3, 3, 3, 3, 3]),
+    IN.Spec(d=2, n=[3, 2, 5]),       # periodic axis shorter than 3
+    IN.Spec(d=2, n=[0, 4, 4]),
+    IN.Spec(d=1, n=[4, 4], lens=[1.0, -1.0]),
+    IN.Spec(d=1, n=[4, 4], vkind=7),
+])
+def test_sizes_reject_invalid(bad):
+    from paper_2103_14588_amd import dirac_st as D
+    with pytest.raises(D.DiracError) as e:
+        D.sizes(bad)
+    assert e.value.code == D.EINVAL
+    assert D.last_error()
