@@ -37,6 +37,24 @@ def spmv_bytes(op, cs):
     return op.nnzb * (op.nc * op.nc * cs + 4) + 4 * (op.nrows + 1) + 2 * op.n * cs
 
 
+def counter_traffic(kernel_key):
+    """HBM bytes per launch of the SpMV measured with rocprofv3 counters
+    (profiles/pmc_traffic_2p1d_128cubed.json), or None if the SpMV source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_2p1d_128cubed.json")
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("paper_2103_14588_amd/csrc/spmv.hpp", "paper_2103_14588_amd/csrc/common.hpp"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != doc.get("spmv_source_sha256"):
+        return None
+    k = doc["kernels"].get(kernel_key)
+    return None if k is None else int(k["traffic_bytes"])
+
+
 def time_launches(fn, reps, torch):
     """Average duration of fn() launches on the current stream, HIP events."""
     s = torch.cuda.current_stream()
@@ -78,6 +96,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--only", choices=["spmv64", "spmv32", "assemble", "copy"], default=None,
+                    help="launch only this kernel --kernel-reps times (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -95,6 +115,19 @@ def main():
     psi0 = torch.from_numpy(wl.psi0).cuda()
     op, b = D.assemble(spec, psi0)
     x = torch.zeros_like(b)
+    if args.only:
+        # one kernel, --kernel-reps launches, nothing else on the GPU
+        xx = torch.randn(op.n, dtype=torch.complex128, device="cuda")
+        yy = torch.empty_like(xx)
+        xx32, yy32 = xx.to(torch.complex64), torch.empty(op.n, dtype=torch.complex64, device="cuda")
+        fn = {"spmv64": lambda: D.spmv(op, xx, yy), "spmv32": lambda: D.spmv(op, xx32, yy32),
+              "assemble": lambda: D.assemble_into(op, psi0, b), "copy": lambda: yy.copy_(xx)}[args.only]
+        ms = time_launches(fn, args.kernel_reps, torch)
+        nbytes = {"spmv64": spmv_bytes(op, 16), "spmv32": spmv_bytes(op, 8),
+                  "assemble": op.bytes() + op.n * 16 + psi0.numel() * 16, "copy": 2 * op.n * 16}[args.only]
+        print(json.dumps({"only": args.only, "reps": args.kernel_reps, "ms": ms, "bytes": nbytes,
+                          "GBps": nbytes / ms / 1e6}))
+        return
     o32 = D.make_opts(restart=50, max_it=2000, pc="spectral", precision=32, rtol=1e-8,
                       inner_rtol=1e-5, vbar=0.0)
     o64 = D.make_opts(restart=50, max_it=2000, pc="spectral", precision=64, rtol=1e-8, vbar=0.0)
@@ -181,7 +214,8 @@ def main():
                  "c128_bytes": by64, "c64_bytes": by32},
         "roofline": {"kernel": "spmv_kernel<double,2,16> (BSR SpMV, complex128)", "bound": "hbm",
                      "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": counter_traffic("spmv64"),
+                     "algorithmic_bytes": by64},
         "assembly": {"ms": round(t_asm, 4), "bytes_written": asm_bytes,
                      "GBps": round(asm_bytes / t_asm / 1e6, 1)},
         "memory_GB": round((op.bytes() + work.numel()) / 1e9, 3),

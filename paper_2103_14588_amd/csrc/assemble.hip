@@ -124,47 +124,55 @@ __device__ inline double potential_weight(const AsmParams &P, int e, int b, int 
 }
 
 // Block coupling the row node with coordinates gr (gr[0] = time node tau) to
-// the column node at offsets o (each -1, 0, +1).  blk: nc*nc entries.
-template <int NC>
+// the column node at offsets o (each -1, 0, +1).  DS = spatial dimensions
+// (compile time, so every per-axis array stays in registers).
+template <int NC, int DS>
 __device__ void block_value(const AsmParams &P, const int *gr, const int *o, double2 *blk) {
-  double KM[4], KC[4], KW = 0.0;
-  for (int a = 0; a <= P.d; a++) {
+  double KM[DS + 1], KC[DS + 1], KW = 0.0;
+#pragma unroll
+  for (int a = 0; a <= DS; a++) {
     const int n = P.n[a];
-    int e[2], b[2], al[2], cnt = 0;
-    auto push = [&](int ee, int bb, int aa) {
-      if (a == 0) {
-        if (ee < 0 || ee >= n) return;
-      } else {
-        ee = (ee + n) % n;
-      }
-      e[cnt] = ee;
-      b[cnt] = bb;
-      al[cnt] = aa;
-      cnt++;
-    };
-    if (o[a] == 1) push(gr[a], 0, 1);
-    else if (o[a] == -1) push(gr[a] - 1, 1, 0);
-    else {
-      push(gr[a] - 1, 1, 1);
-      push(gr[a], 0, 0);
-    }
     double km = 0.0, kc = 0.0, kw = 0.0;
-    for (int c = 0; c < cnt; c++) {
-      km += P.M[a][b[c]][al[c]];
-      kc += P.Cd[a][b[c]][al[c]];
-      if (a == 1 && P.vkind != DIRAC_ST_V_NONE) kw += potential_weight(P, e[c], b[c], al[c]);
+    // elements along axis a containing both nodes: offset +1 -> the row
+    // node's element (local 0 -> 1); -1 -> the previous one (1 -> 0);
+    // 0 -> both neighbouring elements (1 -> 1 and 0 -> 0)
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      int e, bb, aa;
+      if (o[a] == 1) {
+        if (c) continue;
+        e = gr[a], bb = 0, aa = 1;
+      } else if (o[a] == -1) {
+        if (c) continue;
+        e = gr[a] - 1, bb = 1, aa = 0;
+      } else {
+        e = c ? gr[a] : gr[a] - 1;
+        bb = c ? 0 : 1;
+        aa = bb;
+      }
+      if (a == 0) {
+        if (e < 0 || e >= n) continue;
+      } else {
+        e = (e + n) % n;
+      }
+      km += P.M[a][bb][aa];
+      kc += P.Cd[a][bb][aa];
+      if (a == 1 && P.vkind != DIRAC_ST_V_NONE) kw += potential_weight(P, e, bb, aa);
     }
     KM[a] = km;
     KC[a] = kc;
     if (a == 1) KW = kw;
   }
-  double Dmu[4], D0 = 1.0, Pw = KW;
-  for (int mu = 0; mu <= P.d; mu++) {
+  double Dmu[DS + 1], D0 = 1.0, Pw = KW;
+#pragma unroll
+  for (int mu = 0; mu <= DS; mu++) {
     double v = 1.0;
-    for (int a = 0; a <= P.d; a++) v *= (a == mu) ? KC[a] : KM[a];
+#pragma unroll
+    for (int a = 0; a <= DS; a++) v *= (a == mu) ? KC[a] : KM[a];
     Dmu[mu] = v;
   }
-  for (int a = 0; a <= P.d; a++) {
+#pragma unroll
+  for (int a = 0; a <= DS; a++) {
     D0 *= KM[a];
     if (a != 1) Pw *= KM[a];
   }
@@ -173,7 +181,8 @@ __device__ void block_value(const AsmParams &P, const int *gr, const int *o, dou
 #pragma unroll
     for (int j = 0; j < NC; j++) {
       double re = 0.0, im = 0.0;
-      for (int mu = 0; mu <= P.d; mu++) {
+#pragma unroll
+      for (int mu = 0; mu <= DS; mu++) {
         double2 gg = P.g[mu][i * NC + j];
         re -= gg.y * Dmu[mu];  // i * g
         im += gg.x * Dmu[mu];
@@ -194,61 +203,82 @@ __device__ inline int spatial_offset(int i, int n, int k) {
 }
 
 // Gauss-Jordan inverse with partial pivoting; returns false if singular or if
-// the 1-norm condition number exceeds 1e12.
+// the 1-norm condition number exceeds 1e12.  Row swaps are unrolled selects.
 template <int NC>
 __device__ bool block_inverse(const double2 *a, double2 *inv) {
   double2 m[NC][2 * NC];
   double na = 0.0;
+#pragma unroll
   for (int j = 0; j < NC; j++) {
     double s = 0.0;
+#pragma unroll
     for (int i = 0; i < NC; i++) s += sqrt(cabs2(a[i * NC + j]));
     na = fmax(na, s);
   }
+#pragma unroll
   for (int i = 0; i < NC; i++)
+#pragma unroll
     for (int j = 0; j < 2 * NC; j++)
       m[i][j] = (j < NC) ? a[i * NC + j] : mk<double2>(j - NC == i ? 1.0 : 0.0, 0.0);
+  bool ok = true;
+#pragma unroll
   for (int c = 0; c < NC; c++) {
+    double best = cabs2(m[c][c]);
     int piv = c;
-    for (int r = c + 1; r < NC; r++)
-      if (cabs2(m[r][c]) > cabs2(m[piv][c])) piv = r;
-    if (cabs2(m[piv][c]) == 0.0) return false;
-    for (int j = 0; j < 2 * NC; j++) {
-      double2 t = m[c][j];
-      m[c][j] = m[piv][j];
-      m[piv][j] = t;
+#pragma unroll
+    for (int r = c + 1; r < NC; r++) {
+      const double v = cabs2(m[r][c]);
+      if (v > best) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (best == 0.0) ok = false;
+#pragma unroll
+    for (int r = c + 1; r < NC; r++) {
+      if (r == piv) {
+#pragma unroll
+        for (int j = 0; j < 2 * NC; j++) {
+          double2 t = m[c][j];
+          m[c][j] = m[r][j];
+          m[r][j] = t;
+        }
+      }
     }
     double2 d = m[c][c];
-    double dd = 1.0 / cabs2(d);
+    double dd = best > 0.0 ? 1.0 / cabs2(d) : 0.0;
     double2 dinv = mk<double2>(d.x * dd, -d.y * dd);
+#pragma unroll
     for (int j = 0; j < 2 * NC; j++) m[c][j] = cmul(m[c][j], dinv);
+#pragma unroll
     for (int r = 0; r < NC; r++) {
       if (r == c) continue;
       double2 f = m[r][c];
+#pragma unroll
       for (int j = 0; j < 2 * NC; j++) m[r][j] = cfms(m[r][j], f, m[c][j]);
     }
   }
   double ni = 0.0;
+#pragma unroll
   for (int j = 0; j < NC; j++) {
     double s = 0.0;
+#pragma unroll
     for (int i = 0; i < NC; i++) s += sqrt(cabs2(m[i][NC + j]));
     ni = fmax(ni, s);
   }
+#pragma unroll
   for (int i = 0; i < NC; i++)
+#pragma unroll
     for (int j = 0; j < NC; j++) inv[i * NC + j] = m[i][NC + j];
-  return na * ni <= 1e12 && isfinite(na * ni);
+  return ok && na * ni <= 1e12 && isfinite(na * ni);
 }
 
-template <int NC>
-__global__ __launch_bounds__(256) void assemble_kernel(AsmParams P, int32_t *__restrict__ row_ptr,
-                                                        int32_t *__restrict__ col_idx,
-                                                        double2 *__restrict__ val64,
-                                                        float2 *__restrict__ val32,
-                                                        double2 *__restrict__ bj64,
-                                                        float2 *__restrict__ bj32,
-                                                        int32_t *__restrict__ nsingular) {
-  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (kb >= P.nnzb) return;
-  int tau, k, c;
+// Block kb of the CSR value array: its row, position k in the row, column
+// node, whether it is the diagonal block, and its values.
+template <int NC, int DS>
+__device__ inline void block_at(const AsmParams &P, int64_t kb, int64_t &r, int &k,
+                                int64_t &colnode, bool &diag, double2 *blk) {
+  int tau, c;
   int64_t s;
   if (kb < P.off_int) {
     tau = 1;
@@ -270,57 +300,85 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams P, int32_t *__r
     s = q / c;
     k = (int)(q - s * c);
   }
-  const int64_t r = (int64_t)(tau - 1) * P.S + s;
-  int gr[4] = {tau, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+  r = (int64_t)(tau - 1) * P.S + s;
+  int gr[DS + 1], o[DS + 1];
+  gr[0] = tau;
   int64_t ss = s;
-  for (int a = 1; a <= P.d; a++) {
+#pragma unroll
+  for (int a = 1; a <= DS; a++) {
     gr[a] = (int)(ss % P.n[a]);
     ss /= P.n[a];
   }
-  // block position k -> offsets: time slowest, then axis d ... axis 1
-  int kt = k / P.sp3, ks = k - kt * P.sp3;
-  {
-    int list[3], nl = 0;
-    if (tau >= 2) list[nl++] = -1;
-    list[nl++] = 0;
-    if (tau <= P.nt - 1) list[nl++] = 1;
-    o[0] = list[kt];
-  }
-  int64_t colnode = (int64_t)(tau + o[0] - 1) * P.S;
-  bool diag = (o[0] == 0);
-  for (int a = 1; a <= P.d; a++) {
-    int dig = ks % 3;
+  // block position k -> offsets: time slowest, then axis d ... axis 1; the
+  // time neighbours present are tau-1 (if tau >= 2), tau, tau+1 (if tau < n_t)
+  const int kt = k / P.sp3;
+  int ks = k - kt * P.sp3;
+  o[0] = kt - (tau >= 2 ? 1 : 0);
+  colnode = (int64_t)(tau + o[0] - 1) * P.S;
+  diag = (o[0] == 0);
+#pragma unroll
+  for (int a = 1; a <= DS; a++) {
+    const int dig = ks % 3;
     ks /= 3;
     o[a] = spatial_offset(gr[a], P.n[a], dig);
     colnode += (int64_t)((gr[a] + o[a] + P.n[a]) % P.n[a]) * P.stride[a];
     diag = diag && (o[a] == 0);
   }
-  double2 blk[NC * NC];
-  block_value<NC>(P, gr, o, blk);
-  double2 *v64 = val64 + kb * NC * NC;
+  block_value<NC, DS>(P, gr, o, blk);
+}
+
+// One thread per stored block.  The workgroup's blocks form one contiguous
+// stretch of the value arrays, so they are staged in LDS and written out with
+// consecutive lanes on consecutive 16-byte (complex128) entries.
+template <int NC, int DS, int BS>
+__global__ __launch_bounds__(BS) void assemble_kernel(AsmParams P, int32_t *__restrict__ row_ptr,
+                                                       int32_t *__restrict__ col_idx,
+                                                       double2 *__restrict__ val64,
+                                                       float2 *__restrict__ val32,
+                                                       double2 *__restrict__ bj64,
+                                                       float2 *__restrict__ bj32,
+                                                       int32_t *__restrict__ nsingular) {
+  __shared__ double2 sblk[BS * NC * NC];
+  const int64_t kb0 = (int64_t)blockIdx.x * BS;
+  const int64_t kb = kb0 + threadIdx.x;
+  if (kb < P.nnzb) {
+    int64_t r, colnode;
+    int k;
+    bool diag;
+    double2 blk[NC * NC];
+    block_at<NC, DS>(P, kb, r, k, colnode, diag, blk);
 #pragma unroll
-  for (int q = 0; q < NC * NC; q++) v64[q] = blk[q];
-  if (val32) {
-    float2 *v32 = val32 + kb * NC * NC;
+    for (int q = 0; q < NC * NC; q++) sblk[threadIdx.x * NC * NC + q] = blk[q];
+    col_idx[kb] = (int32_t)colnode;
+    if (k == 0) row_ptr[r] = (int32_t)kb;
+    if (kb == P.nnzb - 1) row_ptr[P.nrows] = (int32_t)P.nnzb;
+    if (diag && bj64) {
+      double2 inv[NC * NC];
+      if (!block_inverse<NC>(blk, inv)) {
+        atomicAdd(nsingular, 1);
 #pragma unroll
-    for (int q = 0; q < NC * NC; q++) v32[q] = to32(blk[q]);
+        for (int i = 0; i < NC; i++)
+#pragma unroll
+          for (int j = 0; j < NC; j++) inv[i * NC + j] = mk<double2>(i == j ? 1.0 : 0.0, 0.0);
+      }
+      double2 *b64 = bj64 + r * NC * NC;
+#pragma unroll
+      for (int q = 0; q < NC * NC; q++) b64[q] = inv[q];
+      if (bj32) {
+        float2 *b32 = bj32 + r * NC * NC;
+#pragma unroll
+        for (int q = 0; q < NC * NC; q++) b32[q] = to32(inv[q]);
+      }
+    }
   }
-  col_idx[kb] = (int32_t)colnode;
-  if (k == 0) row_ptr[r] = (int32_t)kb;
-  if (kb == P.nnzb - 1) row_ptr[P.nrows] = (int32_t)P.nnzb;
-  if (diag && bj64) {
-    double2 inv[NC * NC];
-    if (!block_inverse<NC>(blk, inv)) {
-      atomicAdd(nsingular, 1);
-      for (int i = 0; i < NC; i++)
-        for (int j = 0; j < NC; j++) inv[i * NC + j] = mk<double2>(i == j ? 1.0 : 0.0, 0.0);
-    }
-    double2 *b64 = bj64 + r * NC * NC;
-    for (int q = 0; q < NC * NC; q++) b64[q] = inv[q];
-    if (bj32) {
-      float2 *b32 = bj32 + r * NC * NC;
-      for (int q = 0; q < NC * NC; q++) b32[q] = to32(inv[q]);
-    }
+  __syncthreads();
+  const int64_t nb = (P.nnzb - kb0) < BS ? (P.nnzb - kb0) : BS;
+  const int nent = (int)nb * NC * NC;
+  double2 *v64 = val64 + kb0 * NC * NC;
+  for (int e = threadIdx.x; e < nent; e += BS) v64[e] = sblk[e];
+  if (val32) {
+    float2 *v32 = val32 + kb0 * NC * NC;
+    for (int e = threadIdx.x; e < nent; e += BS) v32[e] = to32(sblk[e]);
   }
 }
 
@@ -330,34 +388,42 @@ __global__ void zero_i32(int32_t *p, int n) {
 }
 
 // b = -D_w21 psi0: only rows of the first time slice see the t = 0 columns.
-template <int NC>
+template <int NC, int DS>
 __global__ __launch_bounds__(256) void rhs_kernel(AsmParams P, const double2 *__restrict__ psi0,
                                                    double2 *__restrict__ b) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= P.nrows) return;
   double2 acc[NC];
+#pragma unroll
   for (int i = 0; i < NC; i++) acc[i] = mk<double2>(0, 0);
   if (r < P.S) {
-    int gr[4] = {1, 0, 0, 0}, o[4] = {-1, 0, 0, 0};
+    int gr[DS + 1], o[DS + 1];
+    gr[0] = 1;
+    o[0] = -1;
     int64_t ss = r;
-    for (int a = 1; a <= P.d; a++) {
+#pragma unroll
+    for (int a = 1; a <= DS; a++) {
       gr[a] = (int)(ss % P.n[a]);
       ss /= P.n[a];
     }
     for (int ks = 0; ks < P.sp3; ks++) {
       int t = ks;
       int64_t col = 0;
-      for (int a = 1; a <= P.d; a++) {
+#pragma unroll
+      for (int a = 1; a <= DS; a++) {
         o[a] = (t % 3) - 1;
         t /= 3;
         col += (int64_t)((gr[a] + o[a] + P.n[a]) % P.n[a]) * P.stride[a];
       }
       double2 blk[NC * NC];
-      block_value<NC>(P, gr, o, blk);
+      block_value<NC, DS>(P, gr, o, blk);
+#pragma unroll
       for (int i = 0; i < NC; i++)
+#pragma unroll
         for (int j = 0; j < NC; j++) acc[i] = cfma(acc[i], blk[i * NC + j], psi0[col * NC + j]);
     }
   }
+#pragma unroll
   for (int i = 0; i < NC; i++) b[r * NC + i] = mk<double2>(-acc[i].x, -acc[i].y);
 }
 
@@ -382,25 +448,24 @@ extern "C" int dirac_st_assemble(const dirac_st_problem *prob, const void *psi0,
     zero_i32<<<1, 64, 0, st>>>(dsing, 1);
     DST_LAUNCHED();
   }
-  const int bs = 256;
-  const unsigned grid = (unsigned)((P.nnzb + bs - 1) / bs);
-  if (P.nc == 2)
-    assemble_kernel<2><<<grid, bs, 0, st>>>(P, A->row_ptr, A->col_idx, (double2 *)A->val64,
-                                            (float2 *)A->val32, (double2 *)A->bjinv64,
-                                            (float2 *)A->bjinv32, dsing);
-  else
-    assemble_kernel<4><<<grid, bs, 0, st>>>(P, A->row_ptr, A->col_idx, (double2 *)A->val64,
-                                            (float2 *)A->val32, (double2 *)A->bjinv64,
-                                            (float2 *)A->bjinv32, dsing);
-  DST_LAUNCHED();
-  if (b) {
-    const unsigned g2 = (unsigned)((P.nrows + bs - 1) / bs);
-    if (P.nc == 2)
-      rhs_kernel<2><<<g2, bs, 0, st>>>(P, (const double2 *)psi0, (double2 *)b);
-    else
-      rhs_kernel<4><<<g2, bs, 0, st>>>(P, (const double2 *)psi0, (double2 *)b);
-    DST_LAUNCHED();
+  const unsigned g256 = (unsigned)((P.nnzb + 255) / 256);
+  const unsigned grow = (unsigned)((P.nrows + 255) / 256);
+  double2 *v64 = (double2 *)A->val64, *bj64 = (double2 *)A->bjinv64;
+  float2 *v32 = (float2 *)A->val32, *bj32 = (float2 *)A->bjinv32;
+  const double2 *ps = (const double2 *)psi0;
+  double2 *bb = (double2 *)b;
+  if (P.d == 1) {
+    assemble_kernel<2, 1, 256><<<g256, 256, 0, st>>>(P, A->row_ptr, A->col_idx, v64, v32, bj64, bj32, dsing);
+    if (b) rhs_kernel<2, 1><<<grow, 256, 0, st>>>(P, ps, bb);
+  } else if (P.d == 2) {
+    assemble_kernel<2, 2, 256><<<g256, 256, 0, st>>>(P, A->row_ptr, A->col_idx, v64, v32, bj64, bj32, dsing);
+    if (b) rhs_kernel<2, 2><<<grow, 256, 0, st>>>(P, ps, bb);
+  } else {
+    assemble_kernel<4, 3, 128><<<(unsigned)((P.nnzb + 127) / 128), 128, 0, st>>>(
+        P, A->row_ptr, A->col_idx, v64, v32, bj64, bj32, dsing);
+    if (b) rhs_kernel<4, 3><<<grow, 256, 0, st>>>(P, ps, bb);
   }
+  DST_LAUNCHED();
   A->nc = prob->nc;
   A->prob = *prob;
   A->singular_blocks = 0;

@@ -211,10 +211,14 @@ static int pc_setup(Precond &P, const dirac_st_bsr *A, int kind, double vbar, un
   spec_geom(&A->prob, vbar, P.G);
   if (int rc = spec_twiddles(P.G, spec, P.SL, s)) return rc;
   const unsigned g = (unsigned)((P.G.S + 63) / 64);
-  if (A->nc == 2)
-    spectral_setup<T, 2><<<g, 64, 0, s>>>(P.G, (const double2 *)(spec + P.SL.tw64), (cx<T> *)(spec + P.SL.piv));
+  const double2 *tw64 = (const double2 *)(spec + P.SL.tw64);
+  cx<T> *piv = (cx<T> *)(spec + P.SL.piv);
+  if (A->prob.d == 1)
+    spectral_setup<T, 2, 1><<<g, 64, 0, s>>>(P.G, tw64, piv);
+  else if (A->prob.d == 2)
+    spectral_setup<T, 2, 2><<<g, 64, 0, s>>>(P.G, tw64, piv);
   else
-    spectral_setup<T, 4><<<g, 64, 0, s>>>(P.G, (const double2 *)(spec + P.SL.tw64), (cx<T> *)(spec + P.SL.piv));
+    spectral_setup<T, 4, 3><<<g, 64, 0, s>>>(P.G, tw64, piv);
   DST_LAUNCHED();
   return 0;
 }
@@ -253,9 +257,17 @@ static int pc_apply(const Precond &P, const cx<T> *v, cx<T> *z, double scale, in
         const bool first = (pass == 0 && a == 1);
         const bool last = (pass == 1 && a == G.d);
         const T sc = last ? (T)(scale / (double)G.S) : (T)1;
-        dft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(first ? v : z, z, n, stride, ti, ntq,
-                                                            pass == 0 ? -1 : 1, sc,
-                                                            tw + G.tw_off[a]);
+        if ((n & (n - 1)) == 0) {
+          int logn = 0;
+          while ((1 << logn) < n) logn++;
+          fft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(first ? v : z, z, n, logn, stride, ti,
+                                                              ntq, pass == 0 ? -1 : 1, sc,
+                                                              tw + G.tw_off[a]);
+        } else {
+          dft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(first ? v : z, z, n, stride, ti, ntq,
+                                                              pass == 0 ? -1 : 1, sc,
+                                                              tw + G.tw_off[a]);
+        }
         DST_LAUNCHED();
         stride *= n;
       }
@@ -263,10 +275,12 @@ static int pc_apply(const Precond &P, const cx<T> *v, cx<T> *z, double scale, in
         const unsigned g = (unsigned)((G.S + 63) / 64);
         const double2 *tw64 = (const double2 *)(P.spec + P.SL.tw64);
         const cx<T> *piv = (const cx<T> *)(P.spec + P.SL.piv);
-        if (nc == 2)
-          spectral_thomas<T, 2><<<g, 64, 0, s>>>(G, tw64, piv, z);
+        if (G.d == 1)
+          spectral_thomas<T, 2, 1><<<g, 64, 0, s>>>(G, tw64, piv, z);
+        else if (G.d == 2)
+          spectral_thomas<T, 2, 2><<<g, 64, 0, s>>>(G, tw64, piv, z);
         else
-          spectral_thomas<T, 4><<<g, 64, 0, s>>>(G, tw64, piv, z);
+          spectral_thomas<T, 4, 3><<<g, 64, 0, s>>>(G, tw64, piv, z);
         DST_LAUNCHED();
       }
     }

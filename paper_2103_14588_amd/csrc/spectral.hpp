@@ -60,12 +60,14 @@ inline SpecLayout spec_layout(const dirac_st_problem *p, int prec) {
   return L;
 }
 
+template <int NC, int DS>
 __device__ inline void mode_blocks(const SpecGeom &G, int64_t s, const double2 *tw, double2 *L,
                                    double2 *U, double2 *Dint, double2 *Dlast) {
-  double mu[4], sn[4];
+  double mu[DS + 1], sn[DS + 1];
   int64_t t = s;
   double mus = 1.0;
-  for (int a = 1; a <= G.d; a++) {
+#pragma unroll
+  for (int a = 1; a <= DS; a++) {
     const int k = (int)(t % G.n[a]);
     t /= G.n[a];
     const double2 w = tw[G.tw_off[a] + k];  // exp(-i th)
@@ -73,14 +75,16 @@ __device__ inline void mode_blocks(const SpecGeom &G, int64_t s, const double2 *
     sn[a] = -w.y;
     mus *= mu[a];
   }
-  const int nc = G.nc;
   const double ht = G.h[0];
-  for (int q = 0; q < nc * nc; q++) {
-    const int i = q / nc, j = q % nc;
+#pragma unroll
+  for (int q = 0; q < NC * NC; q++) {
+    const int i = q / NC, j = q % NC;
     double sr = 0.0, si = 0.0;
-    for (int a = 1; a <= G.d; a++) {
+#pragma unroll
+    for (int a = 1; a <= DS; a++) {
       double other = 1.0;
-      for (int b = 1; b <= G.d; b++)
+#pragma unroll
+      for (int b = 1; b <= DS; b++)
         if (b != a) other *= mu[b];
       // i g^a (i sin th_a) other = -g^a sin th_a other
       sr -= G.g[a][q].x * sn[a] * other;
@@ -100,122 +104,197 @@ __device__ inline void mode_blocks(const SpecGeom &G, int64_t s, const double2 *
 
 template <int NC>
 __device__ inline void matmul_nc(const double2 *a, const double2 *b, double2 *c) {
+#pragma unroll
   for (int i = 0; i < NC; i++)
+#pragma unroll
     for (int j = 0; j < NC; j++) {
       double2 s = mk<double2>(0, 0);
+#pragma unroll
       for (int k = 0; k < NC; k++) s = cfma(s, a[i * NC + k], b[k * NC + j]);
       c[i * NC + j] = s;
     }
 }
 
-// Gauss-Jordan inverse with partial pivoting (no conditioning guard).
+// Gauss-Jordan inverse with partial pivoting (no conditioning guard); the
+// row swap is an unrolled select so the matrix stays in registers.
 template <int NC>
 __device__ inline void inverse_nc(const double2 *a, double2 *inv) {
   double2 m[NC][2 * NC];
+#pragma unroll
   for (int i = 0; i < NC; i++)
+#pragma unroll
     for (int j = 0; j < 2 * NC; j++)
       m[i][j] = (j < NC) ? a[i * NC + j] : mk<double2>(j - NC == i ? 1.0 : 0.0, 0.0);
+#pragma unroll
   for (int c = 0; c < NC; c++) {
+    double best = cabs2(m[c][c]);
     int piv = c;
-    for (int r = c + 1; r < NC; r++)
-      if (cabs2(m[r][c]) > cabs2(m[piv][c])) piv = r;
-    for (int j = 0; j < 2 * NC; j++) {
-      double2 t = m[c][j];
-      m[c][j] = m[piv][j];
-      m[piv][j] = t;
+#pragma unroll
+    for (int r = c + 1; r < NC; r++) {
+      const double v = cabs2(m[r][c]);
+      if (v > best) {
+        best = v;
+        piv = r;
+      }
+    }
+#pragma unroll
+    for (int r = c + 1; r < NC; r++) {
+      if (r == piv) {
+#pragma unroll
+        for (int j = 0; j < 2 * NC; j++) {
+          double2 t = m[c][j];
+          m[c][j] = m[r][j];
+          m[r][j] = t;
+        }
+      }
     }
     double2 d = m[c][c];
     double dd = 1.0 / cabs2(d);
     double2 dinv = mk<double2>(d.x * dd, -d.y * dd);
+#pragma unroll
     for (int j = 0; j < 2 * NC; j++) m[c][j] = cmul(m[c][j], dinv);
+#pragma unroll
     for (int r = 0; r < NC; r++) {
       if (r == c) continue;
       double2 f = m[r][c];
+#pragma unroll
       for (int j = 0; j < 2 * NC; j++) m[r][j] = cfms(m[r][j], f, m[c][j]);
     }
   }
+#pragma unroll
   for (int i = 0; i < NC; i++)
+#pragma unroll
     for (int j = 0; j < NC; j++) inv[i * NC + j] = m[i][NC + j];
 }
 
 // Pivot inverses of the block elimination along time, one thread per mode.
-template <typename T, int NC>
+template <typename T, int NC, int DS>
 __global__ __launch_bounds__(64) void spectral_setup(SpecGeom G, const double2 *__restrict__ tw,
                                                      cx<T> *__restrict__ piv) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= G.S) return;
   double2 L[NC * NC], U[NC * NC], Di[NC * NC], Dl[NC * NC], P[NC * NC], Pinv[NC * NC],
       t1[NC * NC], t2[NC * NC];
-  mode_blocks(G, s, tw, L, U, Di, Dl);
+  mode_blocks<NC, DS>(G, s, tw, L, U, Di, Dl);
   for (int tau = 0; tau < G.nt; tau++) {
-    const double2 *D = (tau == G.nt - 1) ? Dl : Di;
+    const bool last = (tau == G.nt - 1);
     if (tau == 0) {
-      for (int q = 0; q < NC * NC; q++) P[q] = D[q];
+#pragma unroll
+      for (int q = 0; q < NC * NC; q++) P[q] = last ? Dl[q] : Di[q];
     } else {
       matmul_nc<NC>(L, Pinv, t1);
       matmul_nc<NC>(t1, U, t2);
-      for (int q = 0; q < NC * NC; q++) P[q] = csub(D[q], t2[q]);
+#pragma unroll
+      for (int q = 0; q < NC * NC; q++) P[q] = csub(last ? Dl[q] : Di[q], t2[q]);
     }
     inverse_nc<NC>(P, Pinv);
     cx<T> *o = piv + ((int64_t)tau * G.S + s) * NC * NC;
+#pragma unroll
     for (int q = 0; q < NC * NC; q++) o[q] = mk<cx<T>>((T)Pinv[q].x, (T)Pinv[q].y);
   }
 }
 
 // Block elimination along time for every mode, in place on data
-// ([nt][S][NC] in the spatial-frequency domain).
-template <typename T, int NC>
+// ([nt][S][NC] in the spatial-frequency domain).  One thread per mode; the
+// time loop is cut into batches of PF steps whose loads (right-hand side rows
+// and pivot inverses) are all issued before the batch's dependent arithmetic,
+// so PF memory latencies overlap.
+template <typename T, int NC, int DS>
 __global__ __launch_bounds__(64) void spectral_thomas(SpecGeom G, const double2 *__restrict__ tw,
                                                       const cx<T> *__restrict__ piv,
                                                       cx<T> *__restrict__ data) {
   using C = cx<T>;
+  constexpr int PF = (NC == 2) ? 8 : (sizeof(T) == 4 ? 2 : 1);
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= G.S) return;
   double2 L64[NC * NC], U64[NC * NC], Di[NC * NC], Dl[NC * NC];
-  mode_blocks(G, s, tw, L64, U64, Di, Dl);
+  mode_blocks<NC, DS>(G, s, tw, L64, U64, Di, Dl);
   C Lm[NC * NC], Um[NC * NC];
+#pragma unroll
   for (int q = 0; q < NC * NC; q++) {
     Lm[q] = mk<C>((T)L64[q].x, (T)L64[q].y);
     Um[q] = mk<C>((T)U64[q].x, (T)U64[q].y);
   }
+  const int nt = G.nt;
+  const int64_t rs = G.S * NC, ps = G.S * NC * NC;
+  C *col = data + s * NC;
+  const C *pcol = piv + s * NC * NC;
   // forward: y_tau = r_tau - L P^{-1}_{tau-1} y_{tau-1}
   C prev[NC];
-  for (int tau = 0; tau < G.nt; tau++) {
-    C *row = data + ((int64_t)tau * G.S + s) * NC;
-    C r[NC];
-    for (int i = 0; i < NC; i++) r[i] = row[i];
-    if (tau > 0) {
-      const C *P = piv + ((int64_t)(tau - 1) * G.S + s) * NC * NC;
-      C z[NC];
-      for (int i = 0; i < NC; i++) {
-        z[i] = mk<C>(0, 0);
-        for (int j = 0; j < NC; j++) z[i] = cfma(z[i], P[i * NC + j], prev[j]);
+  for (int t0 = 0; t0 < nt; t0 += PF) {
+    C rb[PF][NC], pb[PF][NC * NC];
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int tau = t0 + u;
+      if (tau < nt) {
+#pragma unroll
+        for (int i = 0; i < NC; i++) rb[u][i] = col[tau * rs + i];
+        if (tau > 0) {
+#pragma unroll
+          for (int q = 0; q < NC * NC; q++) pb[u][q] = pcol[(tau - 1) * ps + q];
+        }
       }
-      for (int i = 0; i < NC; i++)
-        for (int j = 0; j < NC; j++) r[i] = cfms(r[i], Lm[i * NC + j], z[j]);
     }
-    for (int i = 0; i < NC; i++) {
-      row[i] = r[i];
-      prev[i] = r[i];
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int tau = t0 + u;
+      if (tau < nt) {
+        if (tau > 0) {
+          C z[NC];
+#pragma unroll
+          for (int i = 0; i < NC; i++) {
+            z[i] = mk<C>(0, 0);
+#pragma unroll
+            for (int j = 0; j < NC; j++) z[i] = cfma(z[i], pb[u][i * NC + j], prev[j]);
+          }
+#pragma unroll
+          for (int i = 0; i < NC; i++)
+#pragma unroll
+            for (int j = 0; j < NC; j++) rb[u][i] = cfms(rb[u][i], Lm[i * NC + j], z[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < NC; i++) {
+          col[tau * rs + i] = rb[u][i];
+          prev[i] = rb[u][i];
+        }
+      }
     }
   }
   // backward: x_tau = P^{-1}_tau (y_tau - U x_{tau+1})
-  for (int tau = G.nt - 1; tau >= 0; tau--) {
-    C *row = data + ((int64_t)tau * G.S + s) * NC;
-    C r[NC];
-    for (int i = 0; i < NC; i++) r[i] = row[i];
-    if (tau < G.nt - 1)
-      for (int i = 0; i < NC; i++)
-        for (int j = 0; j < NC; j++) r[i] = cfms(r[i], Um[i * NC + j], prev[j]);
-    const C *P = piv + ((int64_t)tau * G.S + s) * NC * NC;
-    C x[NC];
-    for (int i = 0; i < NC; i++) {
-      x[i] = mk<C>(0, 0);
-      for (int j = 0; j < NC; j++) x[i] = cfma(x[i], P[i * NC + j], r[j]);
+  for (int t0 = nt - 1; t0 >= 0; t0 -= PF) {
+    C rb[PF][NC], pb[PF][NC * NC];
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int tau = t0 - u;
+      if (tau >= 0) {
+#pragma unroll
+        for (int i = 0; i < NC; i++) rb[u][i] = col[tau * rs + i];
+#pragma unroll
+        for (int q = 0; q < NC * NC; q++) pb[u][q] = pcol[tau * ps + q];
+      }
     }
-    for (int i = 0; i < NC; i++) {
-      row[i] = x[i];
-      prev[i] = x[i];
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int tau = t0 - u;
+      if (tau >= 0) {
+        if (tau < nt - 1)
+#pragma unroll
+          for (int i = 0; i < NC; i++)
+#pragma unroll
+            for (int j = 0; j < NC; j++) rb[u][i] = cfms(rb[u][i], Um[i * NC + j], prev[j]);
+        C x[NC];
+#pragma unroll
+        for (int i = 0; i < NC; i++) {
+          x[i] = mk<C>(0, 0);
+#pragma unroll
+          for (int j = 0; j < NC; j++) x[i] = cfma(x[i], pb[u][i * NC + j], rb[u][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < NC; i++) {
+          col[tau * rs + i] = x[i];
+          prev[i] = x[i];
+        }
+      }
     }
   }
 }
@@ -255,6 +334,51 @@ __global__ __launch_bounds__(256) void dft_axis(const cx<T> *in, cx<T> *out, int
       if (idx >= n) idx -= n;
     }
     out[base + (int64_t)k * stride + q] = mk<C>(acc.x * scale, acc.y * scale);
+  }
+}
+
+// Radix-2 decimation-in-time FFT along one axis of power-of-two length n
+// (same element layout and tiling as dft_axis).  The tile is loaded in
+// bit-reversed order into LDS and log2(n) butterfly stages run in place.
+template <typename T>
+__global__ __launch_bounds__(256) void fft_axis(const cx<T> *in, cx<T> *out, int n, int logn,
+                                                int64_t stride, int ti, int ntile_q, int sign,
+                                                T scale, const cx<T> *__restrict__ tw) {
+  using C = cx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C *tile = reinterpret_cast<C *>(smem_raw);  // [n][ti]
+  C *twl = tile + (size_t)n * ti;             // [n/2]
+  const int64_t o = blockIdx.x / ntile_q;
+  const int64_t q0 = (int64_t)(blockIdx.x % ntile_q) * ti;
+  const int64_t base = o * n * stride + q0;
+  for (int t = threadIdx.x; t < n * ti; t += blockDim.x) {
+    const int j = t / ti, q = t % ti;
+    const int jr = (int)(__brev((unsigned)j) >> (32 - logn));
+    tile[jr * ti + q] = in[base + (int64_t)j * stride + q];
+  }
+  for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+    C w = tw[t];
+    twl[t] = mk<C>(w.x, sign < 0 ? w.y : -w.y);
+  }
+  __syncthreads();
+  for (int len = 2, lstep = n / 2; len <= n; len <<= 1, lstep >>= 1) {
+    const int half = len >> 1;
+    for (int t = threadIdx.x; t < (n / 2) * ti; t += blockDim.x) {
+      const int q = t % ti, k = t / ti;
+      const int grp = k / half, pos = k - grp * half;
+      const int i0 = grp * len + pos, i1 = i0 + half;
+      const C w = twl[pos * lstep];
+      const C a = tile[i0 * ti + q], b = tile[i1 * ti + q];
+      const C tb = cmul(w, b);
+      tile[i0 * ti + q] = cadd(a, tb);
+      tile[i1 * ti + q] = csub(a, tb);
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < n * ti; t += blockDim.x) {
+    const int k = t / ti, q = t % ti;
+    const C v = tile[k * ti + q];
+    out[base + (int64_t)k * stride + q] = mk<C>(v.x * scale, v.y * scale);
   }
 }
 

@@ -60,15 +60,37 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, int64_t nwg,
   const int i = (lane / IB) % NC;
   const int jc = lane % IB;
   const int bofs = lane / CPB;
+  // a row holds at most 3^(d+1) blocks: 27 (2x2 blocks, d <= 2) or 81 (4x4, d = 3)
+  constexpr int MAXB = NC == 2 ? 27 : 81;
+  constexpr int MAXIT = (MAXB + BPI - 1) / BPI;
+  constexpr int UNR = MAXIT < 8 ? MAXIT : 8;
   cx<T> acc = mk<cx<T>>(0, 0);
   if (row < nrows) {
     const int rs = rp[row], re = rp[row + 1];
     const Ch *vbase = reinterpret_cast<const Ch *>(val + i * NC + jc * J);
-    for (int b = rs + bofs; b < re; b += BPI) {
-      Ch v = __builtin_nontemporal_load(vbase + (int64_t)b * (NC * NC / J));
-      const int c = ci[b];
-      Ch xv = *reinterpret_cast<const Ch *>(x + (int64_t)c * NC + jc * J);
-      acc = chunk_mac<T>(acc, v, xv);
+    // batches of UNR slices: all value, index and x loads of a batch are in
+    // flight before its first multiply
+    for (int b0 = rs + bofs; b0 < re; b0 += UNR * BPI) {
+      Ch v[UNR], xv[UNR];
+      int c[UNR];
+#pragma unroll
+      for (int it = 0; it < UNR; it++) {
+        const int b = b0 + it * BPI;
+        if (b < re) {
+          v[it] = __builtin_nontemporal_load(vbase + (int64_t)b * (NC * NC / J));
+          c[it] = ci[b];
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < UNR; it++) {
+        const int b = b0 + it * BPI;
+        if (b < re) xv[it] = *reinterpret_cast<const Ch *>(x + (int64_t)c[it] * NC + jc * J);
+      }
+#pragma unroll
+      for (int it = 0; it < UNR; it++) {
+        const int b = b0 + it * BPI;
+        if (b < re) acc = chunk_mac<T>(acc, v[it], xv[it]);
+      }
     }
   }
 #pragma unroll
