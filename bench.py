@@ -89,6 +89,53 @@ def cpu_baseline(wl, x_gpu_list):
                       "(%d iterations, relres %.2e)" % (info["iters"], info["relres"])}, errs
 
 
+def klein_bench(args):
+    """2+1D 128^3 Klein step (V0 = 2.5 m): the learned preconditioner trained on
+    the GPU on 2k (residual, error) pairs from plain GMRES restart iterates on
+    32^3-64^3 Klein-step systems, then FGMRES(50) (complex64 inner cycles, FP64
+    refinement) to 1e-8 with node-block Jacobi, node-block Jacobi + network,
+    node-block Jacobi + untrained network, spectral, spectral + network."""
+    import torch
+    from paper_2103_14588_amd import dirac_st as D
+    from paper_2103_14588_amd import inputs as IN
+    from paper_2103_14588_amd import nnpc
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    pairs = nnpc.make_pairs(n_systems=250, per_system=8, nmin=32, nmax=64, base="bj", restart=20, seed=1)
+    gain, pairs = nnpc.normalise_targets(pairs)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    val = nnpc.make_pairs(n_systems=4, per_system=4, nmin=48, nmax=48, base="bj", restart=20, seed=99)
+    val = [(s, x, (t / gain).contiguous()) for s, x, t in val]
+    net, ctrl = D.Net(nnpc.he_init(0)), D.Net(nnpc.he_init(0), training=False)
+    net.s.out_gain = ctrl.s.out_gain = gain
+    l0 = nnpc.eval_loss(ctrl, val)
+    t0 = time.perf_counter()
+    losses = nnpc.train(net, pairs, epochs=2, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    l1 = nnpc.eval_loss(net, val)
+    del pairs
+
+    wl = IN.klein_step_2p1(128, v0=2.5, seed=0)
+    op, b = D.assemble(wl.spec, torch.from_numpy(wl.psi0).cuda())
+    runs = {}
+    cap = args.max_it
+    for name, pc, nn in (("bj", "bj", None), ("bj+nn", "bj", net), ("bj+untrained_nn", "bj", ctrl),
+                         ("spectral", "spectral", None), ("spectral+nn", "spectral", net)):
+        x, info = D.fgmres_nn(op, b, nn, restart=50, max_it=cap, rtol=1e-8, pc=pc, vbar=1.25,
+                              precision=32, inner_rtol=1e-5)
+        runs[name] = {"iters": info["iters"], "relres": info["relres"], "converged": info["converged"],
+                      "ms": round(info["ms"], 1), "fallback": info["fallback"]}
+        print(name, runs[name], file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "2+1D 128^3 Klein step V0=2.5, FGMRES(50) FP32-IR to 1e-8, cap %d" % cap,
+                      "train": {"pairs": 2000, "gen_s": round(t_gen, 2), "train_s": round(t_train, 2),
+                                "steps": len(losses), "gain": gain, "heldout_untrained": l0,
+                                "heldout_trained": l1},
+                      "runs": runs}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,7 +145,13 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--only", choices=["spmv64", "spmv32", "assemble", "copy"], default=None,
                     help="launch only this kernel --kernel-reps times (for counter runs)")
+    ap.add_argument("--workload", choices=["packet", "klein"], default="packet",
+                    help="packet: the 2+1D 128^3 packet step (default bench line); klein: the "
+                         "learned-preconditioner comparison on the 128^3 Klein step")
+    ap.add_argument("--max-it", type=int, default=1500)
     args = ap.parse_args()
+    if args.workload == "klein":
+        return klein_bench(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); "
               "run it with --gpus 1", file=sys.stderr)

@@ -141,7 +141,70 @@ typedef struct {
   double *history;      /* host, optional (NULL): residual estimate / ||b|| after
                            each Arnoldi step, up to history_len entries */
   int32_t history_len;
+  int32_t fallback;     /* dirac_st_fgmres_nn: 1 if the network was switched off
+                           (non-finite output or a cycle that cut the residual by
+                           less than 1%) and the base preconditioner finished */
 } dirac_st_stats;
+
+/* Learned preconditioner network (2+1D fields only): 3x3x3 convolutions over
+ * the spacetime grid [tau][y][x] with channels 4 -> 16 -> 16 -> 16 -> 4 (real
+ * and imaginary parts of the two spinor components), ReLU between layers,
+ * periodic padding in space and zero padding in time.  bfloat16 weights and
+ * activations, FP32 accumulation on the matrix cores; FP32 master parameters
+ * and Adam state.  All arrays are caller-owned device memory. */
+typedef struct {
+  float *params;        /* [17332]: per layer W[27][cin][cout] then b[cout]; tap
+                           (dt+1)*9 + (dy+1)*3 + (dx+1) */
+  float *adam_m;        /* [17332] first moments (training only, else NULL) */
+  float *adam_v;        /* [17332] second moments (training only, else NULL) */
+  uint16_t *w16;        /* [17280] bf16 weights, written by dirac_st_nn_pack */
+  uint16_t *wt16;       /* [17280] bf16 weights with flipped taps and swapped
+                           channel order (backward pass), written by dirac_st_nn_pack */
+  int32_t step;         /* host: Adam steps taken (incremented by train_step) */
+  float out_gain;       /* host: fixed output gain g of the preconditioner term,
+                           z += g s N(v / s); chosen at training time so that the
+                           network's targets are O(1) (0 is read as 1) */
+} dirac_st_nn;
+
+/* Number of FP32 parameters of the network (17332). */
+size_t dirac_st_nn_param_count(void);
+
+/* Device workspace of the network on an nt x ny x nx grid (training != 0: the
+ * forward-backward pass of dirac_st_nn_train_step / dirac_st_nn_backward). */
+size_t dirac_st_nn_workspace_bytes(int32_t nt, int32_t ny, int32_t nx, int32_t training);
+
+/* Refresh w16 and wt16 from params (round to nearest even). */
+int dirac_st_nn_pack(const dirac_st_nn *net, void *stream);
+
+/* out = N(in_scale * in).  in, out: [nt][ny][nx][4] FP32 (a complex64 field
+ * [nt][ny][nx][2] has this layout). */
+int dirac_st_nn_forward(const dirac_st_nn *net, int32_t nt, int32_t ny, int32_t nx, const float *in,
+                        double in_scale, float *out, void *work, size_t work_bytes, void *stream);
+
+/* grad = d/dparams of <dout, N(in_scale * in)> (dout rounded to bf16 first,
+ * like the training step).  grad: [17332] FP32. */
+int dirac_st_nn_backward(const dirac_st_nn *net, int32_t nt, int32_t ny, int32_t nx, const float *in,
+                         double in_scale, const float *dout, float *grad, void *work,
+                         size_t work_bytes, void *stream);
+
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the loss
+ * ||N(in) - target||^2 / ||target||^2, then dirac_st_nn_pack.  loss_out: device
+ * double receiving the loss before the step (may be NULL). */
+int dirac_st_nn_train_step(dirac_st_nn *net, int32_t nt, int32_t ny, int32_t nx, const float *in,
+                           const float *target, float lr, double *loss_out, void *work,
+                           size_t work_bytes, void *stream);
+
+/* Flexible GMRES(m) (right preconditioning with the preconditioned vectors
+ * Z stored, x += Z y) for a 2+1D operator.  The preconditioner is
+ * z = M^{-1} v + g s N(v / s) with M the base preconditioner opts->pc, g = net->out_gain and
+ * s = ||v|| / sqrt(n) (n complex entries); net == NULL drops the network term.
+ * If the network produces NaN/Inf or a cycle cuts the residual by less than
+ * 1%, the network is switched off for the rest of the solve
+ * (stats->fallback = 1).  The network workspace is part of `work`
+ * (dirac_st_workspace_bytes with flexible = 1).  Returns as dirac_st_gmres. */
+int dirac_st_fgmres_nn(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_nn *net,
+                       const dirac_st_opts *opts, void *work, size_t work_bytes,
+                       dirac_st_stats *stats, void *stream);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *dirac_st_last_error(void);
@@ -173,9 +236,11 @@ int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x, void *y, v
 int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec, double vbar, const void *v,
                       void *z, void *work, size_t work_bytes, void *stream);
 
-/* Bytes of device workspace needed by dirac_st_gmres for these options
- * (basis of restart+1 vectors in the working precision, partial sums,
- * Hessenberg data, preconditioner data). */
+/* Bytes of device workspace needed by dirac_st_gmres (flexible = 0) or
+ * dirac_st_fgmres_nn (flexible = 1) for these options: basis of restart+1
+ * vectors in the working precision, partial sums, Hessenberg data,
+ * preconditioner data; flexible adds the restart preconditioned vectors and,
+ * for 2+1D operators, the network's inference workspace. */
 size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *opts, int32_t flexible);
 
 /* Restarted GMRES(m) with right preconditioning (Sec. 2.2; Alg. 1 step 6):

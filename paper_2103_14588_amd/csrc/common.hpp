@@ -103,6 +103,8 @@ int64_t spatial_nodes(const dirac_st_problem *p);
 int blocks_per_row(const dirac_st_problem *p, int tau);
 int64_t total_blocks(const dirac_st_problem *p);
 
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
 // Rows handled by one XCD stay contiguous: hardware dispatches workgroup b to
 // XCD b % 8, so logical tile = position inside that XCD's share.
 __device__ inline int64_t xcd_tile(int64_t b, int64_t nwg) {

@@ -21,6 +21,7 @@
 
 #include "common.hpp"
 #include "krylov.hpp"
+#include "nn_host.hpp"
 #include "spectral.hpp"
 #include "spmv.hpp"
 
@@ -91,11 +92,11 @@ static hipError_t launch_updots(int mk, const cx<T> *V, int64_t ldv, int jp1, cx
 
 // ------------------------------------------------------------ layout
 struct GmresLayout {
-  size_t V, z, u, r64, partial, ctrl, spec, total;
+  size_t V, z, u, r64, partial, ctrl, spec, Z, nn, total;
   int64_t ldv;  // elements between basis vectors
 };
 
-static GmresLayout gmres_layout(const dirac_st_bsr *A, const dirac_st_opts *o) {
+static GmresLayout gmres_layout(const dirac_st_bsr *A, const dirac_st_opts *o, bool flexible) {
   GmresLayout L{};
   const int64_t N = A->nrows * A->nc;
   const size_t cs = o->precision == 32 ? 8 : 16;
@@ -116,6 +117,11 @@ static GmresLayout gmres_layout(const dirac_st_bsr *A, const dirac_st_opts *o) {
   off += align256(sizeof(Ctrl));
   L.spec = off;
   if (o->pc == DIRAC_ST_PC_SPECTRAL) off += spec_layout(&A->prob, o->precision).total;
+  L.Z = off;
+  if (flexible) off += vb * (size_t)o->restart;
+  L.nn = off;
+  if (flexible && A->prob.d == 2)
+    off += nn_layout(A->prob.n[0], A->prob.n[2], A->prob.n[1], false).total;
   L.total = off;
   return L;
 }
@@ -129,6 +135,10 @@ struct Precond {
   SpecGeom G{};
   unsigned char *spec = nullptr;
   SpecLayout SL{};
+  // learned correction z += s N(v / s) (flexible GMRES only)
+  const dirac_st_nn *nn = nullptr;
+  bool nn_on = false;
+  unsigned char *nnwork = nullptr;
 };
 
 static void spec_geom(const dirac_st_problem *p, double vbar, SpecGeom &G) {
@@ -223,10 +233,10 @@ static int pc_setup(Precond &P, const dirac_st_bsr *A, int kind, double vbar, un
   return 0;
 }
 
-// z = scale * M^{-1} v  (v, z must differ)
+// z = scale * M^{-1} v with the base preconditioner (v, z must differ)
 template <typename T>
-static int pc_apply(const Precond &P, const cx<T> *v, cx<T> *z, double scale, int64_t N,
-                    hipStream_t s) {
+static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scale, int64_t N,
+                         hipStream_t s) {
   const dirac_st_bsr *A = P.A;
   if (P.kind == DIRAC_ST_PC_BLOCK_JACOBI) {
     const cx<T> *binv = (const cx<T> *)(sizeof(T) == 8 ? A->bjinv64 : A->bjinv32);
@@ -290,6 +300,28 @@ static int pc_apply(const Precond &P, const cx<T> *v, cx<T> *z, double scale, in
   return DIRAC_ST_EINVAL;
 }
 
+// Full preconditioner on the true vector scale * v (unit norm in GMRES):
+// base part plus, when the network is on, (1/sqrt(n)) N(sqrt(n) scale v).
+template <typename T>
+static int pc_apply(const Precond &P, const cx<T> *v, cx<T> *z, double scale, int64_t N,
+                    hipStream_t s) {
+  const bool base = P.kind != DIRAC_ST_PC_NONE;
+  if (base)
+    if (int rc = pc_apply_base<T>(P, v, z, scale, N, s)) return rc;
+  if (P.nn_on) {
+    const dirac_st_problem &p = P.A->prob;
+    const double rn = sqrt((double)N);
+    return nn_apply_add(P.nn, p.n[0], p.n[2], p.n[1], v, sizeof(T) == 8 ? 64 : 32, rn * scale,
+                        (P.nn->out_gain != 0.f ? (double)P.nn->out_gain : 1.0) / rn, z, base ? 1 : 0,
+                        P.nnwork, s);
+  }
+  if (!base) {
+    set_error("no preconditioner to apply");
+    return DIRAC_ST_EINVAL;
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------ GMRES
 struct Readback {
   double est_abs, happy, finite, sigma_next;
@@ -297,24 +329,31 @@ struct Readback {
 
 template <typename T>
 static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const dirac_st_opts *o,
-                      unsigned char *work, dirac_st_stats *st, hipStream_t s) {
+                      unsigned char *work, dirac_st_stats *st, hipStream_t s, bool flexible,
+                      const dirac_st_nn *net) {
   using C = cx<T>;
   const auto t_start = std::chrono::steady_clock::now();
   const int nc = A->nc;
   const int64_t N = A->nrows * nc;
   const int m = o->restart;
-  const GmresLayout L = gmres_layout(A, o);
+  const GmresLayout L = gmres_layout(A, o, flexible);
   C *V = (C *)(work + L.V);
   C *z = (C *)(work + L.z);
   C *u = (C *)(work + L.u);
   double2 *r64 = (double2 *)(work + L.r64);
   double2 *partial = (double2 *)(work + L.partial);
   Ctrl *ctrl = (Ctrl *)(work + L.ctrl);
+  C *Zb = (C *)(work + L.Z);
   const int64_t nblk = nblocks(N);
   const void *val = sizeof(T) == 8 ? A->val64 : A->val32;
 
   Precond P;
   if (int rc = pc_setup<T>(P, A, o->pc, o->vbar, work + L.spec, s)) return rc;
+  if (net) {
+    P.nn = net;
+    P.nn_on = true;
+    P.nnwork = work + L.nn;
+  }
   zero_ctrl<<<8, 256, 0, s>>>(ctrl);
   DST_LAUNCHED();
 
@@ -335,6 +374,8 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   S.iters = S.cycles = S.converged = 0;
   S.singular_blocks = A->singular_blocks;
   S.relres = S.est = 0.0;
+  S.fallback = 0;
+  double relres_prev = -1.0;
 
   double bnorm = 0.0;
   if (int rc = read_norm(b, bnorm)) return rc;
@@ -368,6 +409,12 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       rc_final = DIRAC_ST_OK;
       break;
     }
+    // network fallback: a cycle that cut the residual by less than 1%
+    if (P.nn_on && relres_prev > 0.0 && S.relres > 0.99 * relres_prev) {
+      P.nn_on = false;
+      S.fallback = 1;
+    }
+    relres_prev = S.relres;
     if (its >= o->max_it || (o->max_cycles > 0 && S.cycles >= o->max_cycles)) break;
     S.cycles++;
     if (sizeof(T) == 8) {
@@ -384,12 +431,20 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       C *vj = V + (int64_t)j * L.ldv;
       C *w = V + (int64_t)(j + 1) * L.ldv;
       // w = A M^{-1} v_j
-      if (P.kind == DIRAC_ST_PC_NONE) {
+      if (P.kind == DIRAC_ST_PC_NONE && !P.nn_on && !flexible) {
         DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, vj, nullptr, w,
                                (T)sigma_j, false, s));
+      } else if (P.kind == DIRAC_ST_PC_NONE && !P.nn_on) {
+        // flexible without any preconditioner: z_j = v_j
+        C *zj = Zb + (int64_t)j * L.ldv;
+        scale_copy<T><<<nblocks(N), 256, 0, s>>>(vj, sigma_j, zj, N);
+        DST_LAUNCHED();
+        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, zj, nullptr, w, (T)1,
+                               false, s));
       } else {
-        if (int rc = pc_apply<T>(P, vj, z, sigma_j, N, s)) return rc;
-        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, z, nullptr, w, (T)1,
+        C *zj = flexible ? Zb + (int64_t)j * L.ldv : z;
+        if (int rc = pc_apply<T>(P, vj, zj, sigma_j, N, s)) return rc;
+        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, zj, nullptr, w, (T)1,
                                false, s));
       }
       const int jp1 = j + 1, mk = maxk_bucket(jp1);
@@ -427,15 +482,25 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       if (est <= o->rtol || rb.happy != 0.0) break;
       if (sizeof(T) == 4 && o->inner_rtol > 0.0 && rb.est_abs <= o->inner_rtol * rn) break;
     }
+    if (broke && P.nn_on) {
+      // network output not finite: drop this cycle, continue with the base
+      P.nn_on = false;
+      S.fallback = 1;
+      relres_prev = -1.0;
+      continue;
+    }
     if (broke) {
       set_error("NaN or Inf in the Arnoldi process");
       rc_final = DIRAC_ST_EBREAKDOWN;
       break;
     }
-    // x += M^{-1} V y
-    back_substitute<<<1, 64, 0, s>>>(ctrl, k);
+    // x += M^{-1} V y  (flexible: x += Z y)
+    back_substitute<<<1, 64, 0, s>>>(ctrl, k, flexible ? 1 : 0);
     DST_LAUNCHED();
-    if (P.kind == DIRAC_ST_PC_NONE) {
+    if (flexible) {
+      combine<T, double, true><<<nblocks(N), 256, 0, s>>>(Zb, L.ldv, k, ctrl->coef, x, N);
+      DST_LAUNCHED();
+    } else if (P.kind == DIRAC_ST_PC_NONE) {
       combine<T, double, true><<<nblocks(N), 256, 0, s>>>(V, L.ldv, k, ctrl->coef, x, N);
       DST_LAUNCHED();
     } else {
@@ -486,11 +551,10 @@ extern "C" int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x,
 extern "C" size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *o,
                                            int32_t flexible) {
   if (!A || !o || (A->nc != 2 && A->nc != 4)) return 0;
-  (void)flexible;
   dirac_st_opts oo = *o;
   if (oo.restart < 1) oo.restart = 1;
   if (oo.restart > kMaxRestart) oo.restart = kMaxRestart;
-  return gmres_layout(A, &oo).total;
+  return gmres_layout(A, &oo, flexible != 0).total;
 }
 
 extern "C" int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec, double vbar,
@@ -534,7 +598,7 @@ extern "C" int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x,
   DST_CHECK(opts->pc >= 0 && opts->pc <= 2, "unknown preconditioner %d", opts->pc);
   DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
   DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
-  const size_t need = gmres_layout(A, opts).total;
+  const size_t need = gmres_layout(A, opts, false).total;
   if (work_bytes < need) {
     set_error("workspace too small: %zu < %zu bytes", work_bytes, need);
     return DIRAC_ST_ENOSPACE;
@@ -543,7 +607,37 @@ extern "C" int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x,
   hipStream_t s = (hipStream_t)stream;
   if (opts->precision == 64)
     return gmres_impl<double>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work,
-                              stats, s);
+                              stats, s, false, nullptr);
   return gmres_impl<float>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work, stats,
-                           s);
+                           s, false, nullptr);
+}
+
+extern "C" int dirac_st_fgmres_nn(const dirac_st_bsr *A, const void *b, void *x,
+                                  const dirac_st_nn *net, const dirac_st_opts *opts, void *work,
+                                  size_t work_bytes, dirac_st_stats *stats, void *stream) {
+  clear_error();
+  if (int rc = check_bsr(A)) return rc;
+  DST_CHECK(opts != nullptr, "opts is NULL");
+  DST_CHECK(b && x && work, "b, x and work must be set");
+  DST_CHECK(opts->restart >= 1 && opts->restart <= kMaxRestart, "restart must be in 1..%d",
+            kMaxRestart);
+  DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
+  DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
+  DST_CHECK(opts->pc >= 0 && opts->pc <= 2, "unknown preconditioner %d", opts->pc);
+  DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
+  DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
+  DST_CHECK(!net || A->prob.d == 2, "the network preconditioner is for 2+1D operators");
+  DST_CHECK(!net || (net->params && net->w16 && net->wt16), "network arrays are NULL");
+  const size_t need = gmres_layout(A, opts, true).total;
+  if (work_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", work_bytes, need);
+    return DIRAC_ST_ENOSPACE;
+  }
+  DST_CHECK(((uintptr_t)work & 255) == 0, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (opts->precision == 64)
+    return gmres_impl<double>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work,
+                              stats, s, true, net);
+  return gmres_impl<float>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work, stats,
+                           s, true, net);
 }

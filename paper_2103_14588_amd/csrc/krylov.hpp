@@ -260,8 +260,9 @@ __global__ void givens_step(Ctrl *ctrl, int j) {
   ctrl->finite = (isfinite(est) && isfinite(hn)) ? 1.0 : 0.0;
 }
 
-// R y = g (k x k upper triangular), then coef_i = sigma_i y_i.
-__global__ void back_substitute(Ctrl *ctrl, int k) {
+// R y = g (k x k upper triangular), then coef_i = sigma_i y_i (flexible:
+// coef_i = y_i, the stored preconditioned vectors already carry the scale).
+__global__ void back_substitute(Ctrl *ctrl, int k, int flexible) {
   if (threadIdx.x != 0) return;
   for (int i = k - 1; i >= 0; i--) {
     double2 s = ctrl->g[i];
@@ -270,7 +271,7 @@ __global__ void back_substitute(Ctrl *ctrl, int k) {
     double dd = 1.0 / cabs2(d);
     ctrl->y[i] = cmul(s, mk<double2>(d.x * dd, -d.y * dd));
   }
-  for (int i = 0; i < k; i++) ctrl->coef[i] = cscale(ctrl->y[i], ctrl->sigma[i]);
+  for (int i = 0; i < k; i++) ctrl->coef[i] = flexible ? ctrl->y[i] : cscale(ctrl->y[i], ctrl->sigma[i]);
   for (int i = k; i <= kMaxRestart; i++) ctrl->coef[i] = mk<double2>(0, 0);
 }
 
@@ -284,6 +285,15 @@ __global__ __launch_bounds__(256) void combine(const cx<T> *__restrict__ V, int6
   double2 acc = ACCUM ? to64(out[e]) : mk<double2>(0, 0);
   for (int k = 0; k < nk; k++) acc = cfma(acc, to64(V[(int64_t)k * ldv + e]), coef[k]);
   out[e] = mk<cx<TO>>((TO)acc.x, (TO)acc.y);
+}
+
+// z[e] = s * v[e]
+template <typename T>
+__global__ __launch_bounds__(256) void scale_copy(const cx<T> *__restrict__ v, double s,
+                                                   cx<T> *__restrict__ z, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  z[e] = mk<cx<T>>((T)(v[e].x * s), (T)(v[e].y * s));
 }
 
 // x[e] += z[e]

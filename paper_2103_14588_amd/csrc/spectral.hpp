@@ -43,8 +43,6 @@ struct SpecLayout {
   size_t total;
 };
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
 inline SpecLayout spec_layout(const dirac_st_problem *p, int prec) {
   SpecLayout L{};
   int64_t S = 1, twn = 0;

@@ -47,7 +47,13 @@ class Opts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("cycles", C.c_int32), ("converged", C.c_int32),
                 ("singular_blocks", C.c_int32), ("relres", C.c_double), ("est", C.c_double),
-                ("ms", C.c_double), ("history", C.POINTER(C.c_double)), ("history_len", C.c_int32)]
+                ("ms", C.c_double), ("history", C.POINTER(C.c_double)), ("history_len", C.c_int32),
+                ("fallback", C.c_int32)]
+
+
+class NNStruct(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
+                ("w16", C.c_void_p), ("wt16", C.c_void_p), ("step", C.c_int32), ("out_gain", C.c_float)]
 
 
 _vp, _i32, _i64 = C.c_void_p, C.c_int32, C.c_int64
@@ -61,8 +67,24 @@ _lib.dirac_st_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_gmres.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, C.c_size_t,
                                 C.POINTER(Stats), _vp]
 
+_lib.dirac_st_nn_param_count.restype = C.c_size_t
+_lib.dirac_st_nn_workspace_bytes.argtypes = [_i32, _i32, _i32, _i32]
+_lib.dirac_st_nn_workspace_bytes.restype = C.c_size_t
+_lib.dirac_st_nn_pack.argtypes = [C.POINTER(NNStruct), _vp]
+_lib.dirac_st_nn_forward.argtypes = [C.POINTER(NNStruct), _i32, _i32, _i32, _vp, C.c_double, _vp, _vp,
+                                     C.c_size_t, _vp]
+_lib.dirac_st_nn_backward.argtypes = [C.POINTER(NNStruct), _i32, _i32, _i32, _vp, C.c_double, _vp, _vp,
+                                      _vp, C.c_size_t, _vp]
+_lib.dirac_st_nn_train_step.argtypes = [C.POINTER(NNStruct), _i32, _i32, _i32, _vp, _vp, C.c_float, _vp,
+                                        _vp, C.c_size_t, _vp]
+_lib.dirac_st_fgmres_nn.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(NNStruct), C.POINTER(Opts), _vp,
+                                    C.c_size_t, C.POINTER(Stats), _vp]
+
 EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_st_spmv",
-           "dirac_st_pc_apply", "dirac_st_workspace_bytes", "dirac_st_gmres"]
+           "dirac_st_pc_apply", "dirac_st_workspace_bytes", "dirac_st_gmres",
+           "dirac_st_nn_param_count", "dirac_st_nn_workspace_bytes", "dirac_st_nn_pack",
+           "dirac_st_nn_forward", "dirac_st_nn_backward", "dirac_st_nn_train_step",
+           "dirac_st_fgmres_nn"]
 
 
 class DiracError(RuntimeError):
@@ -232,6 +254,94 @@ def gmres(op: Operator, b: torch.Tensor, x: torch.Tensor | None = None, opts: Op
     _check(rc, allow=(OK, NOT_CONVERGED))
     info = dict(rc=rc, iters=st.iters, cycles=st.cycles, converged=bool(st.converged),
                 relres=st.relres, est=st.est, ms=st.ms, singular_blocks=st.singular_blocks)
+    if hist is not None:
+        info["history"] = [hist[i] for i in range(min(st.iters, history))]
+    return x, info
+
+
+# ------------------------------------------------------------------ network
+NN_PARAMS = int(_lib.dirac_st_nn_param_count())
+NN_WEIGHTS = 27 * (4 * 16 + 16 * 16 + 16 * 16 + 16 * 4)
+
+
+class Net:
+    """Network parameters in device memory (FP32 master, bf16 copies, Adam state)."""
+
+    def __init__(self, params, training=True):
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1).to("cuda").contiguous()
+        assert p.numel() == NN_PARAMS
+        self.params = p
+        self.m = torch.zeros_like(p) if training else None
+        self.v = torch.zeros_like(p) if training else None
+        self.w16 = torch.empty(NN_WEIGHTS, dtype=torch.int16, device="cuda")
+        self.wt16 = torch.empty(NN_WEIGHTS, dtype=torch.int16, device="cuda")
+        self.s = NNStruct(params=p.data_ptr(), adam_m=self.m.data_ptr() if training else None,
+                          adam_v=self.v.data_ptr() if training else None, w16=self.w16.data_ptr(),
+                          wt16=self.wt16.data_ptr(), step=0, out_gain=1.0)
+        _check(_lib.dirac_st_nn_pack(C.byref(self.s), _stream()))
+
+    def repack(self):
+        _check(_lib.dirac_st_nn_pack(C.byref(self.s), _stream()))
+
+
+def nn_workspace_bytes(nt, ny, nx, training=False):
+    return int(_lib.dirac_st_nn_workspace_bytes(nt, ny, nx, 1 if training else 0))
+
+
+def _work(nbytes, work):
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+    return work
+
+
+def nn_forward(net: Net, x: torch.Tensor, shape, scale=1.0, work=None):
+    """x: float32 [nt*ny*nx*4] on device; shape (nt, ny, nx)."""
+    nt, ny, nx = shape
+    out = torch.empty_like(x)
+    work = _work(nn_workspace_bytes(nt, ny, nx), work)
+    _check(_lib.dirac_st_nn_forward(C.byref(net.s), nt, ny, nx, _ptr(x), scale, _ptr(out), _ptr(work),
+                                    work.numel(), _stream()))
+    return out
+
+
+def nn_backward(net: Net, x, dout, shape, scale=1.0, work=None):
+    nt, ny, nx = shape
+    grad = torch.empty(NN_PARAMS, dtype=torch.float32, device="cuda")
+    work = _work(nn_workspace_bytes(nt, ny, nx, True), work)
+    _check(_lib.dirac_st_nn_backward(C.byref(net.s), nt, ny, nx, _ptr(x), scale, _ptr(dout), _ptr(grad),
+                                     _ptr(work), work.numel(), _stream()))
+    return grad
+
+
+def nn_train_step(net: Net, x, target, shape, lr, loss_out=None, work=None):
+    nt, ny, nx = shape
+    work = _work(nn_workspace_bytes(nt, ny, nx, True), work)
+    _check(_lib.dirac_st_nn_train_step(C.byref(net.s), nt, ny, nx, _ptr(x), _ptr(target), lr,
+                                       _ptr(loss_out), _ptr(work), work.numel(), _stream()))
+    return work
+
+
+def fgmres_nn(op: Operator, b, net: Net | None, x=None, opts: Opts | None = None, work=None,
+              history: int = 0, **kw):
+    """dirac_st_fgmres_nn.  Returns (x, stats dict)."""
+    if opts is None:
+        opts = make_opts(**kw)
+    if x is None:
+        x = torch.zeros_like(b)
+    nbytes = workspace_bytes(op, opts, flexible=True)
+    work = _work(nbytes, work)
+    st = Stats()
+    hist = None
+    if history:
+        hist = (C.c_double * history)()
+        st.history = C.cast(hist, C.POINTER(C.c_double))
+        st.history_len = history
+    rc = _lib.dirac_st_fgmres_nn(C.byref(op.bsr), _ptr(b), _ptr(x),
+                                 C.byref(net.s) if net is not None else None, C.byref(opts),
+                                 _ptr(work), work.numel(), C.byref(st), _stream())
+    _check(rc, allow=(OK, NOT_CONVERGED))
+    info = dict(rc=rc, iters=st.iters, cycles=st.cycles, converged=bool(st.converged),
+                relres=st.relres, est=st.est, ms=st.ms, fallback=bool(st.fallback))
     if hist is not None:
         info["history"] = [hist[i] for i in range(min(st.iters, history))]
     return x, info
