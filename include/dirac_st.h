@@ -253,6 +253,64 @@ size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *opts
 int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_opts *opts,
                    void *work, size_t work_bytes, dirac_st_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent systems (Alg. 1 run for several initial fields, meshes or
+ * potentials) solved together: every phase of an Arnoldi step is one launch
+ * for the whole batch, its workgroups spread over the systems' tiles.
+ * All systems of a batch must have the same block size nc (same d). */
+
+/* Maximum number of systems in one batched call. */
+#define DIRAC_ST_MAX_BATCH 1024
+
+/* Host.  Workspace bytes of dirac_st_fgmres_batched for these systems and
+ * options (0 on invalid input, see dirac_st_last_error).  A: host array of
+ * nsys host pointers to assembled operators. */
+size_t dirac_st_batched_workspace_bytes(int32_t nsys, const dirac_st_bsr *const *A,
+                                        const dirac_st_opts *opts);
+
+/* Flexible GMRES(m) (Sec. 2.2; Alg. 1 step 6), the same Arnoldi process as
+ * dirac_st_gmres (two classical Gram-Schmidt passes, complex Givens
+ * rotations, FP64 true residual at every restart, inner cycles in complex64
+ * when opts->precision == 32 and x += Z y in FP64), run in lockstep over nsys
+ * systems A[i] x[i] = b[i].  A system leaves the current cycle when its
+ * residual estimate meets rtol (or inner_rtol for precision 32) or on a happy
+ * breakdown, and retires when its FP64 residual meets rtol, or when it reaches
+ * max_it / max_cycles; the others go on.  The base preconditioner opts->pc is
+ * set up per system; for DIRAC_ST_PC_SPECTRAL a negative opts->vbar means
+ * "half of that system's v0".  The SpMV lanes per block row are chosen by an
+ * autotuner: the first call for a (nc, precision, batch size class) times each
+ * candidate on the batch and caches the fastest for the process (see
+ * dirac_st_batched_set_lanes).
+ * A, b, x: host arrays of nsys pointers (b[i], x[i] device complex128
+ * [nrows_i][nc]; x[i] is the initial guess on entry).  stats: host array of
+ * nsys entries (history is not recorded; ms is the time of the whole batch).
+ * work: device, 256-byte aligned, dirac_st_batched_workspace_bytes bytes.
+ * Returns DIRAC_ST_OK when every system converged, DIRAC_ST_NOT_CONVERGED when
+ * some did not (statistics tell which), DIRAC_ST_EBREAKDOWN if NaN/Inf appeared
+ * in some system (the others are still solved), or an argument error. */
+int dirac_st_fgmres_batched(int32_t nsys, const dirac_st_bsr *const *A, const void *const *b,
+                            void *const *x, const dirac_st_opts *opts, void *work, size_t work_bytes,
+                            dirac_st_stats *stats, void *stream);
+
+/* Host.  Workspace bytes of dirac_st_spmv_batched (0 if nsys is out of range). */
+size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys);
+
+/* y[i] = A[i] x[i] for every system in one launch (Sec. 2.2 product).  A, x, y:
+ * host arrays of nsys pointers; x[i], y[i] device vectors of complex128
+ * (prec 64, val64) or complex64 (prec 32, val32).  lanes: lanes per block row,
+ * 4, 8 or 16 for nc = 2; 64 (or 32 at prec 32) for nc = 4.  Enqueues only
+ * (the small descriptor copy is synchronous). */
+int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A, int32_t prec, const void *const *x,
+                          void *const *y, int32_t lanes, void *work, size_t work_bytes, void *stream);
+
+/* Host.  Force the lanes per block row of the batched solver's SpMV for
+ * (nc, prec); 0 returns to autotuning.  Process-wide. */
+int dirac_st_batched_set_lanes(int32_t nc, int32_t prec, int32_t lanes);
+
+/* Host.  Lanes the batched solver uses for a batch of `rows` block rows in total
+ * (forced value, else the autotuned one; 0 if not tuned yet). */
+int32_t dirac_st_batched_lanes(int32_t nc, int32_t prec, int64_t rows);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,740 @@
+// batched.hip -- flexible GMRES(m) over many independent systems of uneven
+// size in grouped launches.
+//
+// Every active system advances through the same Arnoldi step j together.  Each
+// phase of the step -- preconditioner, SpMV, the three Gram-Schmidt passes,
+// the reductions, the Givens update -- is ONE launch for the whole batch: the
+// grid walks a device work list of (system, tile) items and each workgroup
+// reads its system's descriptor (operator, basis, partial sums, FP64 cycle
+// state) before running the same per-tile code as the single-system solver.
+// A system whose residual estimate meets the tolerance (or whose cycle ends on
+// a happy breakdown) drops out of the lists for the rest of the cycle; after
+// each cycle its FP64 true residual decides whether it retires.  Like the
+// single-system solver, inner cycles may run in complex64 (SpMV on val32, basis
+// in complex64) under FP64 refinement: every cycle starts from b - A x in
+// complex128 and adds its correction x += Z y in FP64.
+//
+// The SpMV tile (lanes per block row) is chosen by an autotuner: the first
+// call for a (block size, precision, batch size class) times each candidate
+// on the batch itself with HIP events and caches the fastest.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "krylov.hpp"
+#include "precond.hpp"
+#include "spectral.hpp"
+#include "spmv.hpp"
+
+namespace dst {
+
+struct BSys {
+  const int32_t *rp, *ci;
+  const void *val64, *val32, *bj64, *bj32;
+  int64_t nrows, n, nblk, ldv;
+  void *V;       // m+1 basis vectors, working precision
+  void *Z;       // m preconditioned vectors, working precision
+  double2 *r64;  // FP64 residual
+  double2 *x;
+  const double2 *b;
+  double2 *partial;  // [64][nblk]
+  Ctrl *ctrl;
+  int nc, k;     // block size; steps of the current cycle (set before updates)
+};
+
+constexpr int kMaxBatch = DIRAC_ST_MAX_BATCH;
+
+// Work lists of one launch: the grid's workgroups are numbered 0..off[nact]-1
+// and system act[a] owns workgroups [off[a], off[a+1]).  The offsets are
+// staged in LDS and searched by bisection; the XCD-aware renumbering keeps the
+// tiles an XCD processes contiguous (one system's rows share that XCD's L2).
+struct WorkList {
+  const int64_t *act;  // active systems
+  const int64_t *off;  // nact + 1 prefix sums of workgroups per system
+  int nact;
+};
+
+__device__ inline int find_sys(const WorkList &L, int64_t &local) {
+  __shared__ int64_t so[kMaxBatch + 1];
+  for (int i = threadIdx.x; i <= L.nact; i += blockDim.x) so[i] = L.off[i];
+  __syncthreads();
+  const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
+  int lo = 0, hi = L.nact;  // so[lo] <= bid < so[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (so[mid] <= bid) lo = mid;
+    else hi = mid;
+  }
+  local = bid - so[lo];
+  return (int)L.act[lo];
+}
+
+// ------------------------------------------------------------ grouped kernels
+// mode 0: V_{j+1} = A Z_j (working precision); mode 1: r64 = b - A x (FP64)
+template <typename T, int NC, int G, int MODE>
+__global__ __launch_bounds__(256) void g_spmv(const BSys *__restrict__ S, WorkList L, int j) {
+  int64_t tile;
+  const BSys &s = S[find_sys(L, tile)];
+  if (MODE == 0) {
+    const cx<T> *z = (const cx<T> *)s.Z + (int64_t)j * s.ldv;
+    cx<T> *w = (cx<T> *)s.V + (int64_t)(j + 1) * s.ldv;
+    spmv_tile<T, NC, G, false>(tile, s.nrows, s.rp, s.ci,
+                               (const cx<T> *)(sizeof(T) == 8 ? s.val64 : s.val32), z, nullptr, w,
+                               (T)1);
+  } else {
+    spmv_tile<double, NC, G, true>(tile, s.nrows, s.rp, s.ci, (const double2 *)s.val64, s.x, s.b,
+                                   s.r64, 1.0);
+  }
+}
+
+template <typename T, int MAXK, int MODE>
+__global__ __launch_bounds__(256) void g_cgs(const BSys *__restrict__ S, WorkList L, int jp1) {
+  int64_t blk;
+  const BSys &s = S[find_sys(L, blk)];
+  cx<T> *V = (cx<T> *)s.V;
+  cgs_block<T, MAXK, MODE>(blk, s.nblk, V, s.ldv, jp1, V + (int64_t)jp1 * s.ldv, s.ctrl->coef,
+                           s.partial, s.n);
+}
+
+// partial[0][b] = |r64|^2 (src 0) or |b|^2 (src 1) over the block
+__global__ __launch_bounds__(256) void g_norm(const BSys *__restrict__ S, WorkList L, int src) {
+  __shared__ double red[4];
+  int64_t blk;
+  const BSys &s = S[find_sys(L, blk)];
+  const int64_t e = blk * 256 + threadIdx.x;
+  double v = 0.0;
+  if (e < s.n) v = cabs2(src == 0 ? s.r64[e] : s.b[e]);
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) s.partial[blk] = mk<double2>(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+
+// blockIdx.y -> active system, blockIdx.x -> coefficient
+__global__ __launch_bounds__(256) void g_reduce(const BSys *__restrict__ S, const int64_t *__restrict__ act,
+                                                int what, int which) {
+  const BSys &s = S[act[blockIdx.y]];
+  reduce_coef(blockIdx.x, s.partial, s.nblk, s.ctrl, what, which);
+}
+
+// one workgroup per active system
+__global__ void g_cycle_init(const BSys *__restrict__ S, const int64_t *__restrict__ act) {
+  const BSys &s = S[act[blockIdx.x]];
+  cycle_init_dev(s.ctrl, sqrt(s.ctrl->dots_norm2), 1.0);
+}
+__global__ void g_givens(const BSys *__restrict__ S, const int64_t *__restrict__ act, int j) {
+  givens_dev(S[act[blockIdx.x]].ctrl, j);
+}
+__global__ void g_backsub(const BSys *__restrict__ S, const int64_t *__restrict__ act) {
+  const BSys &s = S[act[blockIdx.x]];
+  backsub_dev(s.ctrl, s.k, 1);
+}
+
+// V_0 = T(r64 / ||r64||)
+template <typename T>
+__global__ __launch_bounds__(256) void g_v0(const BSys *__restrict__ S, WorkList L) {
+  int64_t blk;
+  const BSys &s = S[find_sys(L, blk)];
+  const int64_t e = blk * 256 + threadIdx.x;
+  if (e >= s.n) return;
+  const double inv = 1.0 / sqrt(s.ctrl->dots_norm2);
+  const double2 v = s.r64[e];
+  ((cx<T> *)s.V)[e] = mk<cx<T>>((T)(v.x * inv), (T)(v.y * inv));
+}
+
+// Z_j = sigma_j B^{-1} V_j (node-block Jacobi) or sigma_j V_j (no preconditioner)
+template <typename T, int NC, bool BJ>
+__global__ __launch_bounds__(256) void g_pc_local(const BSys *__restrict__ S, WorkList L, int j) {
+  int64_t blk;
+  const BSys &s = S[find_sys(L, blk)];
+  const int64_t e = blk * 256 + threadIdx.x;
+  if (e >= s.n) return;
+  const T sg = (T)s.ctrl->sigma[j];
+  const cx<T> *v = (const cx<T> *)s.V + (int64_t)j * s.ldv;
+  cx<T> *z = (cx<T> *)s.Z + (int64_t)j * s.ldv;
+  if (!BJ) {
+    z[e] = mk<cx<T>>(v[e].x * sg, v[e].y * sg);
+    return;
+  }
+  const cx<T> *binv = (const cx<T> *)(sizeof(T) == 8 ? s.bj64 : s.bj32);
+  const int64_t r = e / NC;
+  const int i = (int)(e - r * NC);
+  cx<T> acc = mk<cx<T>>(0, 0);
+#pragma unroll
+  for (int q = 0; q < NC; q++) acc = cfma(acc, binv[(r * NC + i) * NC + q], v[r * NC + q]);
+  z[e] = mk<cx<T>>(acc.x * sg, acc.y * sg);
+}
+
+// x += sum_{i < k} Z_i coef_i (FP64 accumulation)
+template <typename T>
+__global__ __launch_bounds__(256) void g_update(const BSys *__restrict__ S, WorkList L) {
+  int64_t blk;
+  const BSys &s = S[find_sys(L, blk)];
+  const int64_t e = blk * 256 + threadIdx.x;
+  if (e >= s.n) return;
+  double2 acc = s.x[e];
+  const cx<T> *Z = (const cx<T> *)s.Z;
+  const double2 *coef = s.ctrl->coef;
+  for (int i = 0; i < s.k; i++) acc = cfma(acc, to64(Z[(int64_t)i * s.ldv + e]), coef[i]);
+  s.x[e] = acc;
+}
+
+// which = 0: Z_0 = 0 (working precision); which = 1: x = 0
+template <typename T>
+__global__ __launch_bounds__(256) void g_zero(const BSys *__restrict__ S, WorkList L, int which) {
+  int64_t blk;
+  const BSys &s = S[find_sys(L, blk)];
+  const int64_t e = blk * 256 + threadIdx.x;
+  if (e >= s.n) return;
+  if (which == 0) ((cx<T> *)s.Z)[e] = mk<cx<T>>(0, 0);
+  else s.x[e] = mk<double2>(0, 0);
+}
+
+// per-system read-back: est_abs, happy, finite, sigma_next, norm^2
+__global__ void g_gather(const BSys *__restrict__ S, const int64_t *__restrict__ act, int nact,
+                         double *__restrict__ out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nact) return;
+  const Ctrl *c = S[act[a]].ctrl;
+  out[5 * a + 0] = c->est_abs;
+  out[5 * a + 1] = c->happy;
+  out[5 * a + 2] = c->finite;
+  out[5 * a + 3] = c->sigma_next;
+  out[5 * a + 4] = c->dots_norm2;
+}
+
+__global__ void g_zero_ctrl(const BSys *__restrict__ S) {
+  double *p = reinterpret_cast<double *>(S[blockIdx.y].ctrl);
+  const int64_t n = sizeof(Ctrl) / sizeof(double);
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------ host side
+struct BatchLayout {
+  std::vector<size_t> V, Z, r64, partial, ctrl, spec;
+  std::vector<int64_t> ldv, nblk;
+  size_t desc, lists, gather, total;
+};
+
+static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const dirac_st_opts *o) {
+  BatchLayout L;
+  const size_t cs = o->precision == 32 ? 8 : 16;
+  const int m = o->restart;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t r = off;
+    off += align256(b);
+    return r;
+  };
+  for (int i = 0; i < nsys; i++) {
+    const int64_t N = A[i]->nrows * A[i]->nc;
+    const size_t vb = align256((size_t)N * cs);
+    L.ldv.push_back((int64_t)(vb / cs));
+    L.nblk.push_back((N + 255) / 256);
+    L.V.push_back(take(vb * (m + 1)));
+    L.Z.push_back(take(vb * m));
+    L.r64.push_back(take((size_t)N * 16));
+    L.partial.push_back(take((size_t)L.nblk.back() * kMaxRestart * sizeof(double2)));
+    L.ctrl.push_back(take(sizeof(Ctrl)));
+    L.spec.push_back(o->pc == DIRAC_ST_PC_SPECTRAL ? take(spec_layout(&A[i]->prob, o->precision).total)
+                                                   : 0);
+  }
+  L.desc = take(sizeof(BSys) * nsys);
+  L.lists = take(sizeof(int64_t) * 4 * (nsys + 1));
+  L.gather = take(sizeof(double) * 5 * nsys);
+  L.total = off;
+  return L;
+}
+
+// Device copies of the work lists of the current set of systems: active
+// systems, then prefix sums of SpMV tiles (working lanes G), FP64-residual
+// SpMV tiles, and 256-element vector blocks.
+struct Lists {
+  int64_t *dev = nullptr;
+  int cap = 0;
+  std::vector<int> cur;
+  int G = -1, Gres = -1;
+  WorkList w{}, r{}, v{};
+  unsigned nw = 0, nr = 0, nv = 0;
+  std::vector<int64_t> host;
+
+  int set(const std::vector<BSys> &hs, const std::vector<int> &act, int g, int gres, hipStream_t s) {
+    if (act == cur && g == G && gres == Gres) return 0;
+    cur = act;
+    G = g;
+    Gres = gres;
+    const int na = (int)act.size();
+    host.assign(4 * (size_t)(cap + 1), 0);
+    int64_t *ha = host.data(), *hw = ha + (cap + 1), *hr = hw + (cap + 1), *hv = hr + (cap + 1);
+    const int64_t rw = 256 / g, rr = 256 / gres;
+    for (int a = 0; a < na; a++) {
+      const BSys &q = hs[act[a]];
+      ha[a] = act[a];
+      hw[a + 1] = hw[a] + (q.nrows + rw - 1) / rw;
+      hr[a + 1] = hr[a] + (q.nrows + rr - 1) / rr;
+      hv[a + 1] = hv[a] + q.nblk;
+    }
+    DST_CHECK(hw[na] < (int64_t(1) << 31) && hv[na] < (int64_t(1) << 31), "batch too large for one grid");
+    nw = (unsigned)hw[na];
+    nr = (unsigned)hr[na];
+    nv = (unsigned)hv[na];
+    w = {dev, dev + (cap + 1), na};
+    r = {dev, dev + 2 * (cap + 1), na};
+    v = {dev, dev + 3 * (cap + 1), na};
+    DST_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // the host staging vector is rewritten by the next call: wait for the copy
+    DST_HIP(hipStreamSynchronize(s));
+    return 0;
+  }
+};
+
+template <typename T, int NC, int MODE>
+static hipError_t launch_g_spmv(int G, const BSys *S, const WorkList &L, unsigned nwg, int j,
+                                hipStream_t s) {
+  if (nwg == 0) return hipSuccess;
+  if (NC == 2) {
+    if (G == 4) g_spmv<T, 2, 4, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+    else if (G == 8) g_spmv<T, 2, 8, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+    else g_spmv<T, 2, 16, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+  } else {
+    if (G == 32 && sizeof(T) == 4) g_spmv<T, 4, 32, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+    else g_spmv<T, 4, 64, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+static hipError_t launch_g_cgs(int mk, const BSys *S, const WorkList &L, unsigned nwg, int jp1,
+                               hipStream_t s) {
+  if (nwg == 0) return hipSuccess;
+  switch (mk) {
+    case 8: g_cgs<T, 8, MODE><<<nwg, 256, 0, s>>>(S, L, jp1); break;
+    case 16: g_cgs<T, 16, MODE><<<nwg, 256, 0, s>>>(S, L, jp1); break;
+    case 32: g_cgs<T, 32, MODE><<<nwg, 256, 0, s>>>(S, L, jp1); break;
+    default:
+      if constexpr (MODE != UPDOTS || sizeof(T) == 4) g_cgs<T, 64, MODE><<<nwg, 256, 0, s>>>(S, L, jp1);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// lanes per block row the SpMV may use, for (block size, precision)
+static std::vector<int> lane_candidates(int nc, int prec) {
+  if (nc == 2) return std::vector<int>{4, 8, 16};
+  return prec == 32 ? std::vector<int>{32, 64} : std::vector<int>{64};
+}
+
+// autotune cache: (nc, precision, floor(log2 of the batch's block rows)) -> lanes
+static std::mutex g_tune_mu;
+static std::map<long, int> g_tune;
+static int g_forced[2][2] = {{0, 0}, {0, 0}};  // [nc == 4][prec == 32]
+
+static long tune_key(int nc, int prec, int64_t rows) {
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= rows) lg++;
+  return (long)nc * 100000 + (long)prec * 100 + lg;
+}
+
+// Pick the SpMV lanes for a batch: a forced value, else the cache, else time
+// every candidate on V_1 = A Z_0 over the whole batch (one warm-up launch and
+// one timed launch each) and keep the fastest.
+template <typename T>
+static int choose_lanes(const std::vector<BSys> &hs, const BSys *dS, Lists &lists,
+                        const std::vector<int> &all, int gres, int &G, hipStream_t s) {
+  const int nc = hs[0].nc, prec = sizeof(T) == 8 ? 64 : 32;
+  int64_t rows = 0;
+  for (const BSys &q : hs) rows += q.nrows;
+  const long key = tune_key(nc, prec, rows);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    G = g_forced[nc == 4][prec == 32];
+    if (G) return 0;
+    auto f = g_tune.find(key);
+    if (f != g_tune.end()) {
+      G = f->second;
+      return 0;
+    }
+  }
+  hipEvent_t e0, e1;
+  DST_HIP(hipEventCreate(&e0));
+  DST_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int rc = 0;
+  for (int c : lane_candidates(nc, prec)) {
+    if ((rc = lists.set(hs, all, c, gres, s))) break;
+    g_zero<T><<<lists.nv, 256, 0, s>>>(dS, lists.v, 0);
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && !rc; rep++) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        e = nc == 2 ? launch_g_spmv<T, 2, 0>(c, dS, lists.w, lists.nw, 0, s)
+                    : launch_g_spmv<T, 4, 0>(c, dS, lists.w, lists.nw, 0, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_error("SpMV autotuning failed: %s", hipGetErrorString(e));
+        rc = DIRAC_ST_EHIP;
+      }
+    }
+    if (!rc && ms < best) {
+      best = ms;
+      G = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = G;
+  return 0;
+}
+
+static void fill_desc(BSys &q, const dirac_st_bsr *A) {
+  q = BSys{};
+  q.rp = A->row_ptr;
+  q.ci = A->col_idx;
+  q.val64 = A->val64;
+  q.val32 = A->val32;
+  q.bj64 = A->bjinv64;
+  q.bj32 = A->bjinv32;
+  q.nrows = A->nrows;
+  q.n = A->nrows * A->nc;
+  q.nblk = (q.n + 255) / 256;
+  q.nc = A->nc;
+}
+
+template <typename T>
+static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *const *b, void *const *x,
+                        const dirac_st_opts *o, unsigned char *work, dirac_st_stats *stats,
+                        hipStream_t s) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const BatchLayout BL = batch_layout(nsys, A, o);
+  const int m = o->restart;
+  const int nc = A[0]->nc;
+  std::vector<BSys> hs(nsys);
+  std::vector<Precond> pcs(nsys);
+  BSys *dS = (BSys *)(work + BL.desc);
+  double *dGat = (double *)(work + BL.gather);
+  Lists lists;
+  lists.dev = (int64_t *)(work + BL.lists);
+  lists.cap = nsys;
+  for (int i = 0; i < nsys; i++) {
+    BSys &q = hs[i];
+    fill_desc(q, A[i]);
+    q.ldv = BL.ldv[i];
+    q.V = work + BL.V[i];
+    q.Z = work + BL.Z[i];
+    q.r64 = (double2 *)(work + BL.r64[i]);
+    q.x = (double2 *)x[i];
+    q.b = (const double2 *)b[i];
+    q.partial = (double2 *)(work + BL.partial[i]);
+    q.ctrl = (Ctrl *)(work + BL.ctrl[i]);
+    if (o->pc != DIRAC_ST_PC_NONE) {
+      const double vbar = o->vbar >= 0.0 ? o->vbar : 0.5 * A[i]->prob.v0;
+      if (int rc = pc_setup<T>(pcs[i], A[i], o->pc, vbar, work + BL.spec[i], s)) return rc;
+    }
+  }
+  auto upload_desc = [&]() -> int {
+    DST_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
+    DST_HIP(hipStreamSynchronize(s));
+    return 0;
+  };
+  if (int rc = upload_desc()) return rc;
+  g_zero_ctrl<<<dim3(4, nsys), 256, 0, s>>>(dS);
+  DST_LAUNCHED();
+
+  std::vector<int> all(nsys);
+  for (int i = 0; i < nsys; i++) all[i] = i;
+  const int Gres = nc == 2 ? 16 : 64;  // FP64 residual SpMV
+  int G = 0;
+  if (int rc = choose_lanes<T>(hs, dS, lists, all, Gres, G, s)) return rc;
+
+  for (int i = 0; i < nsys; i++) stats[i].est = 0.0;
+  std::vector<double> bnorm(nsys, 0.0), relres(nsys, 1.0), rb(5 * (size_t)nsys);
+  std::vector<int> its(nsys, 0), cycles(nsys, 0), conv(nsys, 0), broke(nsys, 0);
+  auto gather = [&](int nact) -> int {
+    g_gather<<<(nact + 63) / 64, 64, 0, s>>>(dS, lists.w.act, nact, dGat);
+    DST_LAUNCHED();
+    DST_HIP(hipMemcpyAsync(rb.data(), dGat, sizeof(double) * 5 * nact, hipMemcpyDeviceToHost, s));
+    DST_HIP(hipStreamSynchronize(s));
+    return 0;
+  };
+  // residual norms of the listed systems into rb[5a + 4]: r64 = b - A x (resid) or ||b||
+  auto norms = [&](bool resid) -> int {
+    const unsigned na = (unsigned)lists.cur.size();
+    if (resid) DST_HIP(nc == 2 ? (launch_g_spmv<double, 2, 1>(Gres, dS, lists.r, lists.nr, 0, s))
+                               : (launch_g_spmv<double, 4, 1>(Gres, dS, lists.r, lists.nr, 0, s)));
+    g_norm<<<lists.nv, 256, 0, s>>>(dS, lists.v, resid ? 0 : 1);
+    g_reduce<<<dim3(1, na), 256, 0, s>>>(dS, lists.w.act, 1, 0);
+    DST_LAUNCHED();
+    return gather((int)na);
+  };
+
+  if (int rc = lists.set(hs, all, G, Gres, s)) return rc;
+  if (int rc = norms(false)) return rc;
+  std::vector<int> active, zero_b;
+  for (int i = 0; i < nsys; i++) {
+    bnorm[i] = sqrt(rb[5 * i + 4]);
+    if (!std::isfinite(bnorm[i])) broke[i] = 1;
+    else if (bnorm[i] == 0.0) zero_b.push_back(i);
+    else active.push_back(i);
+  }
+  if (!zero_b.empty()) {  // b = 0: x = 0 solves the system exactly
+    if (int rc = lists.set(hs, zero_b, G, Gres, s)) return rc;
+    g_zero<T><<<lists.nv, 256, 0, s>>>(dS, lists.v, 1);
+    DST_LAUNCHED();
+    for (int i : zero_b) {
+      conv[i] = 1;
+      relres[i] = 0.0;
+    }
+  }
+
+  std::vector<double> sigma(nsys, 1.0), rstart(nsys, 0.0);
+  while (!active.empty()) {
+    // FP64 true residuals decide convergence and restart
+    if (int rc = lists.set(hs, active, G, Gres, s)) return rc;
+    if (int rc = norms(true)) return rc;
+    std::vector<int> cyc;
+    for (size_t a = 0; a < active.size(); a++) {
+      const int i = active[a];
+      const double rn = sqrt(rb[5 * a + 4]);
+      relres[i] = rn / bnorm[i];
+      rstart[i] = rn;
+      if (!std::isfinite(rn)) broke[i] = 1;
+      else if (relres[i] <= o->rtol) conv[i] = 1;
+      else if (its[i] < o->max_it && (o->max_cycles <= 0 || cycles[i] < o->max_cycles)) cyc.push_back(i);
+    }
+    active = cyc;
+    if (active.empty()) break;
+    // start the cycle: V_0 = r / ||r||, g = ||r|| e_1, sigma_0 = 1
+    if (int rc = lists.set(hs, active, G, Gres, s)) return rc;
+    g_v0<T><<<lists.nv, 256, 0, s>>>(dS, lists.v);
+    g_cycle_init<<<(unsigned)active.size(), 64, 0, s>>>(dS, lists.w.act);
+    DST_LAUNCHED();
+    for (int i : active) {
+      cycles[i]++;
+      sigma[i] = 1.0;
+      hs[i].k = 0;
+    }
+    std::vector<int> step = active;
+    for (int j = 0; j < m && !step.empty(); j++) {
+      if (int rc = lists.set(hs, step, G, Gres, s)) return rc;
+      const unsigned na = (unsigned)step.size();
+      // Z_j = M^{-1} (sigma_j V_j)
+      if (o->pc == DIRAC_ST_PC_SPECTRAL) {
+        for (int i : step) {
+          const cx<T> *vj = (const cx<T> *)hs[i].V + (int64_t)j * hs[i].ldv;
+          cx<T> *zj = (cx<T> *)hs[i].Z + (int64_t)j * hs[i].ldv;
+          if (int rc = pc_apply_base<T>(pcs[i], vj, zj, sigma[i], hs[i].n, s)) return rc;
+        }
+      } else if (o->pc == DIRAC_ST_PC_BLOCK_JACOBI) {
+        if (nc == 2) g_pc_local<T, 2, true><<<lists.nv, 256, 0, s>>>(dS, lists.v, j);
+        else g_pc_local<T, 4, true><<<lists.nv, 256, 0, s>>>(dS, lists.v, j);
+      } else {
+        g_pc_local<T, 2, false><<<lists.nv, 256, 0, s>>>(dS, lists.v, j);
+      }
+      DST_LAUNCHED();
+      // V_{j+1} = A Z_j
+      DST_HIP(nc == 2 ? (launch_g_spmv<T, 2, 0>(G, dS, lists.w, lists.nw, j, s))
+                      : (launch_g_spmv<T, 4, 0>(G, dS, lists.w, lists.nw, j, s)));
+      // two classical Gram-Schmidt passes and the norm, as in the single solver
+      const int jp1 = j + 1;
+      const int mk = jp1 <= 8 ? 8 : jp1 <= 16 ? 16 : jp1 <= 32 ? 32 : 64;
+      DST_HIP((launch_g_cgs<T, DOTS>(mk, dS, lists.v, lists.nv, jp1, s)));
+      g_reduce<<<dim3(jp1, na), 256, 0, s>>>(dS, lists.w.act, 0, 1);
+      DST_LAUNCHED();
+      if (sizeof(T) == 4 || mk <= 32) {
+        DST_HIP((launch_g_cgs<T, UPDOTS>(mk, dS, lists.v, lists.nv, jp1, s)));
+      } else {
+        DST_HIP((launch_g_cgs<T, UPDATE>(mk, dS, lists.v, lists.nv, jp1, s)));
+        DST_HIP((launch_g_cgs<T, DOTS>(mk, dS, lists.v, lists.nv, jp1, s)));
+      }
+      g_reduce<<<dim3(jp1, na), 256, 0, s>>>(dS, lists.w.act, 0, 2);
+      DST_LAUNCHED();
+      DST_HIP((launch_g_cgs<T, UPNORM>(mk, dS, lists.v, lists.nv, jp1, s)));
+      g_reduce<<<dim3(1, na), 256, 0, s>>>(dS, lists.w.act, 1, 0);
+      g_givens<<<na, 64, 0, s>>>(dS, lists.w.act, j);
+      DST_LAUNCHED();
+      if (int rc = gather((int)na)) return rc;
+      std::vector<int> next;
+      for (size_t a = 0; a < step.size(); a++) {
+        const int i = step[a];
+        its[i]++;
+        hs[i].k = j + 1;
+        const double est_abs = rb[5 * a], happy = rb[5 * a + 1], fin = rb[5 * a + 2];
+        sigma[i] = rb[5 * a + 3];
+        stats[i].est = est_abs / bnorm[i];
+        if (fin == 0.0 || !std::isfinite(est_abs)) {
+          broke[i] = 1;
+          continue;
+        }
+        if (stats[i].est <= o->rtol || happy != 0.0 || its[i] >= o->max_it) continue;
+        if (sizeof(T) == 4 && o->inner_rtol > 0.0 && est_abs <= o->inner_rtol * rstart[i]) continue;
+        next.push_back(i);
+      }
+      step = next;
+    }
+    // x += Z y for every system of the cycle that did not break down
+    std::vector<int> upd;
+    for (int i : active)
+      if (!broke[i]) upd.push_back(i);
+    active = upd;
+    if (active.empty()) break;
+    if (int rc = upload_desc()) return rc;  // carries the step counts k
+    if (int rc = lists.set(hs, active, G, Gres, s)) return rc;
+    g_backsub<<<(unsigned)active.size(), 64, 0, s>>>(dS, lists.w.act);
+    g_update<T><<<lists.nv, 256, 0, s>>>(dS, lists.v);
+    DST_LAUNCHED();
+  }
+  DST_HIP(hipStreamSynchronize(s));
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  int rc = DIRAC_ST_OK;
+  for (int i = 0; i < nsys; i++) {
+    stats[i].iters = its[i];
+    stats[i].cycles = cycles[i];
+    stats[i].converged = conv[i];
+    stats[i].singular_blocks = A[i]->singular_blocks;
+    stats[i].relres = relres[i];
+    stats[i].ms = ms;
+    stats[i].fallback = 0;
+    if (broke[i]) rc = DIRAC_ST_EBREAKDOWN;
+    else if (!conv[i] && rc == DIRAC_ST_OK) rc = DIRAC_ST_NOT_CONVERGED;
+  }
+  if (rc == DIRAC_ST_EBREAKDOWN) set_error("NaN or Inf in at least one system of the batch");
+  return rc;
+}
+
+}  // namespace dst
+
+using namespace dst;
+
+static int check_batch(int32_t nsys, const dirac_st_bsr *const *A) {
+  DST_CHECK(nsys >= 1 && nsys <= kMaxBatch && A, "batch size must be in 1..%d", kMaxBatch);
+  for (int i = 0; i < nsys; i++) {
+    DST_CHECK(A[i] && A[i]->row_ptr && A[i]->col_idx && A[i]->val64, "system %d: matrix arrays are NULL", i);
+    DST_CHECK(A[i]->nrows >= 1, "system %d: empty matrix", i);
+    DST_CHECK(A[i]->nc == A[0]->nc, "all systems of a batch must have the same block size");
+  }
+  return 0;
+}
+
+static int check_batch_opts(int32_t nsys, const dirac_st_bsr *const *A, const dirac_st_opts *o) {
+  if (int rc = check_batch(nsys, A)) return rc;
+  DST_CHECK(o, "opts is NULL");
+  DST_CHECK(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in 1..%d", kMaxRestart);
+  DST_CHECK(o->precision == 64 || o->precision == 32, "precision must be 64 or 32");
+  DST_CHECK(o->pc >= DIRAC_ST_PC_NONE && o->pc <= DIRAC_ST_PC_SPECTRAL, "unknown preconditioner %d", o->pc);
+  DST_CHECK(o->rtol > 0.0 && o->max_it >= 0, "rtol must be positive and max_it >= 0");
+  for (int i = 0; i < nsys; i++) {
+    DST_CHECK(o->precision == 64 || A[i]->val32, "system %d: precision 32 needs val32", i);
+    if (o->pc == DIRAC_ST_PC_BLOCK_JACOBI)
+      DST_CHECK(o->precision == 64 ? A[i]->bjinv64 != nullptr : A[i]->bjinv32 != nullptr,
+                "system %d: block-Jacobi preconditioner needs bjinv%d", i, o->precision);
+  }
+  return 0;
+}
+
+extern "C" size_t dirac_st_batched_workspace_bytes(int32_t nsys, const dirac_st_bsr *const *A,
+                                                   const dirac_st_opts *opts) {
+  clear_error();
+  if (check_batch_opts(nsys, A, opts)) return 0;
+  return batch_layout(nsys, A, opts).total;
+}
+
+extern "C" int dirac_st_fgmres_batched(int32_t nsys, const dirac_st_bsr *const *A,
+                                       const void *const *b, void *const *x,
+                                       const dirac_st_opts *opts, void *work, size_t work_bytes,
+                                       dirac_st_stats *stats, void *stream) {
+  clear_error();
+  if (int rc = check_batch_opts(nsys, A, opts)) return rc;
+  DST_CHECK(b && x && work && stats, "b, x, work and stats must be set");
+  for (int i = 0; i < nsys; i++) DST_CHECK(b[i] && x[i], "system %d: b or x is NULL", i);
+  const size_t need = batch_layout(nsys, A, opts).total;
+  if (work_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", work_bytes, need);
+    return DIRAC_ST_ENOSPACE;
+  }
+  DST_CHECK(((uintptr_t)work & 255) == 0, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (opts->precision == 64)
+    return batched_impl<double>(nsys, A, b, x, opts, (unsigned char *)work, stats, s);
+  return batched_impl<float>(nsys, A, b, x, opts, (unsigned char *)work, stats, s);
+}
+
+extern "C" size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys) {
+  clear_error();
+  if (nsys < 1 || nsys > kMaxBatch) {
+    set_error("batch size must be in 1..%d", kMaxBatch);
+    return 0;
+  }
+  return align256(sizeof(BSys) * nsys) + align256(sizeof(int64_t) * 4 * (nsys + 1));
+}
+
+extern "C" int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A, int32_t prec,
+                                     const void *const *x, void *const *y, int32_t lanes, void *work,
+                                     size_t work_bytes, void *stream) {
+  clear_error();
+  if (int rc = check_batch(nsys, A)) return rc;
+  DST_CHECK(prec == 64 || prec == 32, "precision must be 64 or 32");
+  DST_CHECK(x && y && work, "x, y and work must be set");
+  const int nc = A[0]->nc;
+  const std::vector<int> cands = lane_candidates(nc, prec);
+  DST_CHECK(std::find(cands.begin(), cands.end(), (int)lanes) != cands.end(),
+            "lanes %d not available for %dx%d blocks at precision %d", lanes, nc, nc, prec);
+  const size_t need = dirac_st_spmv_batched_workspace_bytes(nsys);
+  if (work_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", work_bytes, need);
+    return DIRAC_ST_ENOSPACE;
+  }
+  DST_CHECK(((uintptr_t)work & 255) == 0, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<BSys> hs(nsys);
+  for (int i = 0; i < nsys; i++) {
+    DST_CHECK(x[i] && y[i], "system %d: x or y is NULL", i);
+    DST_CHECK(prec == 64 || A[i]->val32, "system %d: precision 32 needs val32", i);
+    fill_desc(hs[i], A[i]);
+    hs[i].Z = const_cast<void *>(x[i]);  // V_{j+1} = A Z_j with j = 0 and ldv = 0: y = A x
+    hs[i].V = y[i];
+    hs[i].ldv = 0;
+  }
+  BSys *dS = (BSys *)work;
+  Lists lists;
+  lists.dev = (int64_t *)((unsigned char *)work + align256(sizeof(BSys) * nsys));
+  lists.cap = nsys;
+  DST_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
+  std::vector<int> all(nsys);
+  for (int i = 0; i < nsys; i++) all[i] = i;
+  if (int rc = lists.set(hs, all, lanes, nc == 2 ? 16 : 64, s)) return rc;  // synchronises
+  if (prec == 64)
+    DST_HIP(nc == 2 ? (launch_g_spmv<double, 2, 0>(lanes, dS, lists.w, lists.nw, 0, s))
+                    : (launch_g_spmv<double, 4, 0>(lanes, dS, lists.w, lists.nw, 0, s)));
+  else
+    DST_HIP(nc == 2 ? (launch_g_spmv<float, 2, 0>(lanes, dS, lists.w, lists.nw, 0, s))
+                    : (launch_g_spmv<float, 4, 0>(lanes, dS, lists.w, lists.nw, 0, s)));
+  return 0;
+}
+
+extern "C" int dirac_st_batched_set_lanes(int32_t nc, int32_t prec, int32_t lanes) {
+  clear_error();
+  DST_CHECK((nc == 2 || nc == 4) && (prec == 64 || prec == 32), "nc must be 2 or 4, prec 64 or 32");
+  const std::vector<int> cands = lane_candidates(nc, prec);
+  DST_CHECK(lanes == 0 || std::find(cands.begin(), cands.end(), (int)lanes) != cands.end(),
+            "lanes %d not available for %dx%d blocks at precision %d", lanes, nc, nc, prec);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_forced[nc == 4][prec == 32] = lanes;
+  return 0;
+}
+
+extern "C" int32_t dirac_st_batched_lanes(int32_t nc, int32_t prec, int64_t rows) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int f = (nc == 2 || nc == 4) && (prec == 64 || prec == 32) ? g_forced[nc == 4][prec == 32] : 0;
+  if (f) return f;
+  auto it = g_tune.find(tune_key(nc, prec, rows));
+  return it == g_tune.end() ? 0 : it->second;
+}

@@ -71,13 +71,13 @@ __device__ inline S wave_sum(S v) {
 enum PassMode { DOTS = 0, UPDOTS = 1, UPNORM = 2, UPDATE = 3 };
 
 template <typename T, int MAXK, int MODE>
-__global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int64_t ldv, int jp1,
+__device__ inline void cgs_block(int64_t blk, int64_t nblk, const cx<T> *__restrict__ V, int64_t ldv, int jp1,
                                                  cx<T> *__restrict__ w,
                                                  const double2 *__restrict__ coef,
                                                  double2 *__restrict__ partial, int64_t n) {
   using C = cx<T>;
   __shared__ double red[4][(MAXK < 32 ? MAXK : 32)][2];
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = blk * 256 + threadIdx.x;
   const bool in = e < n;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   C we = in ? w[e] : mk<C>(0, 0);
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int
         const int q = threadIdx.x;
         double2 s = mk<double2>(red[0][q][0] + red[1][q][0] + red[2][q][0] + red[3][q][0],
                                 red[0][q][1] + red[1][q][1] + red[2][q][1] + red[3][q][1]);
-        partial[(int64_t)(t0 + q) * gridDim.x + blockIdx.x] = s;
+        partial[(int64_t)(t0 + q) * nblk + blk] = s;
       }
       __syncthreads();
     }
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int
     if (lane == 0) red[wv][0][0] = s;
     __syncthreads();
     if (threadIdx.x == 0)
-      partial[blockIdx.x] =
+      partial[blk] =
           mk<double2>(red[0][0][0] + red[1][0][0] + red[2][0][0] + red[3][0][0], 0.0);
     return;
   }
@@ -159,22 +159,28 @@ __global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int
         const int q = threadIdx.x;
         double2 s = mk<double2>(red[0][q][0] + red[1][q][0] + red[2][q][0] + red[3][q][0],
                                 red[0][q][1] + red[1][q][1] + red[2][q][1] + red[3][q][1]);
-        partial[(int64_t)(t0 + q) * gridDim.x + blockIdx.x] = s;
+        partial[(int64_t)(t0 + q) * nblk + blk] = s;
       }
       __syncthreads();
     }
   }
 }
 
+template <typename T, int MAXK, int MODE>
+__global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int64_t ldv, int jp1,
+                                                 cx<T> *__restrict__ w,
+                                                 const double2 *__restrict__ coef,
+                                                 double2 *__restrict__ partial, int64_t n) {
+  cgs_block<T, MAXK, MODE>(blockIdx.x, gridDim.x, V, ldv, jp1, w, coef, partial, n);
+}
+
 // Sum partial[k][b] over blocks b (fixed order, FP64); one workgroup per k.
 // Layout: partial[k * nblk + b], contiguous per coefficient.
 // what: 0 -> Gram-Schmidt coefficients into dst (h1 or h2) and coef = sigma_k h_k
 //       1 -> norm^2 into ctrl->dots_norm2
-__global__ __launch_bounds__(256) void reduce_partials(const double2 *__restrict__ partial,
-                                                        int64_t nblk, Ctrl *__restrict__ ctrl,
-                                                        int what, int which) {
+__device__ inline void reduce_coef(int k, const double2 *__restrict__ partial, int64_t nblk,
+                                   Ctrl *__restrict__ ctrl, int what, int which) {
   __shared__ double sx[4], sy[4];
-  const int k = blockIdx.x;
   double ax = 0.0, ay = 0.0;
   for (int64_t b = threadIdx.x; b < nblk; b += 256) {
     double2 v = partial[(int64_t)k * nblk + b];
@@ -201,8 +207,14 @@ __global__ __launch_bounds__(256) void reduce_partials(const double2 *__restrict
   }
 }
 
+static __global__ __launch_bounds__(256) void reduce_partials(const double2 *__restrict__ partial,
+                                                        int64_t nblk, Ctrl *__restrict__ ctrl,
+                                                        int what, int which) {
+  reduce_coef(blockIdx.x, partial, nblk, ctrl, what, which);
+}
+
 // Starts a cycle: g = beta e_1, sigma_0.
-__global__ void cycle_init(Ctrl *ctrl, double beta, double sigma0) {
+__device__ inline void cycle_init_dev(Ctrl *ctrl, double beta, double sigma0) {
   if (threadIdx.x != 0) return;
   for (int i = 0; i <= kMaxRestart; i++) ctrl->g[i] = mk<double2>(0, 0);
   ctrl->g[0] = mk<double2>(beta, 0);
@@ -216,7 +228,7 @@ __global__ void cycle_init(Ctrl *ctrl, double beta, double sigma0) {
 // final norm, previous rotations applied, new complex Givens rotation
 //   rho = sqrt(|a|^2 + |b|^2), c = |a|/rho, s = (a/|a|) conj(b)/rho  (c = 0, s = 1 if a = 0)
 // and the rotated right-hand side; |g_{j+1}| is the residual estimate.
-__global__ void givens_step(Ctrl *ctrl, int j) {
+__device__ inline void givens_dev(Ctrl *ctrl, int j) {
   if (threadIdx.x != 0) return;
   double2 *col = ctrl->H[j];
   double w0 = 0.0;
@@ -262,7 +274,7 @@ __global__ void givens_step(Ctrl *ctrl, int j) {
 
 // R y = g (k x k upper triangular), then coef_i = sigma_i y_i (flexible:
 // coef_i = y_i, the stored preconditioned vectors already carry the scale).
-__global__ void back_substitute(Ctrl *ctrl, int k, int flexible) {
+__device__ inline void backsub_dev(Ctrl *ctrl, int k, int flexible) {
   if (threadIdx.x != 0) return;
   for (int i = k - 1; i >= 0; i--) {
     double2 s = ctrl->g[i];
@@ -330,7 +342,11 @@ __global__ __launch_bounds__(256) void block_jacobi_apply(const cx<T> *__restric
   z[e] = mk<cx<T>>(acc.x * s, acc.y * s);
 }
 
-__global__ void zero_ctrl(Ctrl *ctrl) {
+static __global__ void cycle_init(Ctrl *ctrl, double beta, double sigma0) { cycle_init_dev(ctrl, beta, sigma0); }
+static __global__ void givens_step(Ctrl *ctrl, int j) { givens_dev(ctrl, j); }
+static __global__ void back_substitute(Ctrl *ctrl, int k, int flexible) { backsub_dev(ctrl, k, flexible); }
+
+static __global__ void zero_ctrl(Ctrl *ctrl) {
   double *p = reinterpret_cast<double *>(ctrl);
   const int64_t n = sizeof(Ctrl) / sizeof(double);
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;

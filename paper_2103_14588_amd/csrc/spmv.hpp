@@ -38,14 +38,12 @@ __device__ inline float2 chunk_mac<float>(float2 acc, fv4 v, fv4 x) {
   return cfma(acc, mk<float2>(v.z, v.w), mk<float2>(x.z, x.w));
 }
 
+// Rows [tile * 256/G, (tile + 1) * 256/G) of one operator, one workgroup.
 template <typename T, int NC, int G, bool RESID>
-__global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, int64_t nwg,
-                                                   const int32_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ ci,
-                                                   const cx<T> *__restrict__ val,
-                                                   const cx<T> *__restrict__ x,
-                                                   const cx<T> *__restrict__ bvec,
-                                                   cx<T> *__restrict__ y, T alpha) {
+__device__ inline void spmv_tile(int64_t tile, int64_t nrows, const int32_t *__restrict__ rp,
+                                 const int32_t *__restrict__ ci, const cx<T> *__restrict__ val,
+                                 const cx<T> *__restrict__ x, const cx<T> *__restrict__ bvec,
+                                 cx<T> *__restrict__ y, T alpha) {
   using Ch = typename chunk_of<T>::type;
   constexpr int J = chunk_of<T>::J;
   constexpr int IB = NC / J;          // chunks per block row
@@ -54,7 +52,6 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, int64_t nwg,
   constexpr int RPW = 256 / G;        // rows per workgroup
   constexpr int IMASK = (NC - 1) * IB;
   static_assert(G % CPB == 0 && G <= 64, "group must hold whole blocks");
-  const int64_t tile = xcd_tile(blockIdx.x, nwg);
   const int lane = threadIdx.x % G;
   const int64_t row = tile * RPW + threadIdx.x / G;
   const int i = (lane / IB) % NC;
@@ -108,6 +105,17 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, int64_t nwg,
       y[o] = mk<cx<T>>(alpha * acc.x, alpha * acc.y);
     }
   }
+}
+
+template <typename T, int NC, int G, bool RESID>
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, int64_t nwg,
+                                                   const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const cx<T> *__restrict__ val,
+                                                   const cx<T> *__restrict__ x,
+                                                   const cx<T> *__restrict__ bvec,
+                                                   cx<T> *__restrict__ y, T alpha) {
+  spmv_tile<T, NC, G, RESID>(xcd_tile(blockIdx.x, nwg), nrows, rp, ci, val, x, bvec, y, alpha);
 }
 
 // Host launcher: picks the group size for (T, nc).  resid: y = bvec - A x.

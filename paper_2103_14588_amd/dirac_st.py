@@ -80,11 +80,26 @@ _lib.dirac_st_nn_train_step.argtypes = [C.POINTER(NNStruct), _i32, _i32, _i32, _
 _lib.dirac_st_fgmres_nn.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(NNStruct), C.POINTER(Opts), _vp,
                                     C.c_size_t, C.POINTER(Stats), _vp]
 
+_BSRP = C.POINTER(BSR)
+_lib.dirac_st_batched_workspace_bytes.argtypes = [_i32, C.POINTER(_BSRP), C.POINTER(Opts)]
+_lib.dirac_st_batched_workspace_bytes.restype = C.c_size_t
+_lib.dirac_st_fgmres_batched.argtypes = [_i32, C.POINTER(_BSRP), C.POINTER(_vp), C.POINTER(_vp),
+                                         C.POINTER(Opts), _vp, C.c_size_t, C.POINTER(Stats), _vp]
+_lib.dirac_st_spmv_batched_workspace_bytes.argtypes = [_i32]
+_lib.dirac_st_spmv_batched_workspace_bytes.restype = C.c_size_t
+_lib.dirac_st_spmv_batched.argtypes = [_i32, C.POINTER(_BSRP), _i32, C.POINTER(_vp), C.POINTER(_vp), _i32,
+                                       _vp, C.c_size_t, _vp]
+_lib.dirac_st_batched_set_lanes.argtypes = [_i32, _i32, _i32]
+_lib.dirac_st_batched_lanes.argtypes = [_i32, _i32, _i64]
+_lib.dirac_st_batched_lanes.restype = _i32
+
 EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_st_spmv",
            "dirac_st_pc_apply", "dirac_st_workspace_bytes", "dirac_st_gmres",
            "dirac_st_nn_param_count", "dirac_st_nn_workspace_bytes", "dirac_st_nn_pack",
            "dirac_st_nn_forward", "dirac_st_nn_backward", "dirac_st_nn_train_step",
-           "dirac_st_fgmres_nn"]
+           "dirac_st_fgmres_nn", "dirac_st_batched_workspace_bytes", "dirac_st_fgmres_batched",
+           "dirac_st_spmv_batched_workspace_bytes", "dirac_st_spmv_batched",
+           "dirac_st_batched_set_lanes", "dirac_st_batched_lanes"]
 
 
 class DiracError(RuntimeError):
@@ -345,3 +360,73 @@ def fgmres_nn(op: Operator, b, net: Net | None, x=None, opts: Opts | None = None
     if hist is not None:
         info["history"] = [hist[i] for i in range(min(st.iters, history))]
     return x, info
+
+
+# ------------------------------------------------------------------ batches
+def _bsr_array(ops):
+    arr = (_BSRP * len(ops))()
+    for i, op in enumerate(ops):
+        arr[i] = C.pointer(op.bsr)
+    return arr
+
+
+def _ptr_array(ts):
+    arr = (_vp * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def batched_workspace_bytes(ops, opts: Opts) -> int:
+    n = int(_lib.dirac_st_batched_workspace_bytes(len(ops), _bsr_array(ops), C.byref(opts)))
+    if n == 0:
+        raise DiracError(EINVAL, last_error())
+    return n
+
+
+def fgmres_batched(ops, bs, xs=None, opts: Opts | None = None, work=None, allow_breakdown=False, **kw):
+    """dirac_st_fgmres_batched over the systems ops[i] x_i = b_i.  Returns (xs, list of stats
+    dicts, rc).  Without opts, vbar defaults to -1 (each system uses half its step height).
+    allow_breakdown: return EBREAKDOWN (some system hit NaN/Inf) instead of raising."""
+    if opts is None:
+        kw.setdefault("vbar", -1.0)
+        opts = make_opts(**kw)
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    assert len(ops) == len(bs) == len(xs)
+    A = _bsr_array(ops)
+    nbytes = batched_workspace_bytes(ops, opts)
+    work = _work(nbytes, work)
+    st = (Stats * len(ops))()
+    rc = _lib.dirac_st_fgmres_batched(len(ops), A, _ptr_array(bs), _ptr_array(xs), C.byref(opts),
+                                      _ptr(work), work.numel(), st, _stream())
+    _check(rc, allow=(OK, NOT_CONVERGED, EBREAKDOWN) if allow_breakdown else (OK, NOT_CONVERGED))
+    infos = [dict(iters=s.iters, cycles=s.cycles, converged=bool(s.converged), relres=s.relres,
+                  est=s.est, ms=s.ms) for s in st]
+    return xs, infos, rc
+
+
+def spmv_batched(ops, xs, ys=None, lanes=None, work=None):
+    """dirac_st_spmv_batched: y_i = A_i x_i for every system in one launch."""
+    prec = 64 if xs[0].dtype == torch.complex128 else 32
+    if ys is None:
+        ys = [torch.empty_like(x) for x in xs]
+    if lanes is None:
+        lanes = 16 if ops[0].nc == 2 else 64
+    nbytes = int(_lib.dirac_st_spmv_batched_workspace_bytes(len(ops)))
+    if nbytes == 0:
+        raise DiracError(EINVAL, last_error())
+    work = _work(nbytes, work)
+    _check(_lib.dirac_st_spmv_batched(len(ops), _bsr_array(ops), prec, _ptr_array(xs), _ptr_array(ys),
+                                      lanes, _ptr(work), work.numel(), _stream()))
+    return ys
+
+
+def batched_set_lanes(nc: int, prec: int, lanes: int) -> None:
+    """Force the SpMV lanes per block row of the batched solver (0: autotune)."""
+    _check(_lib.dirac_st_batched_set_lanes(nc, prec, lanes))
+
+
+def batched_lanes(nc: int, prec: int, rows: int) -> int:
+    """Lanes the batched solver uses for a batch of `rows` block rows (0: not tuned yet)."""
+    return int(_lib.dirac_st_batched_lanes(nc, prec, rows))
