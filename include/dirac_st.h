@@ -66,8 +66,14 @@ enum {
 enum {
   DIRAC_ST_PC_NONE = 0,
   DIRAC_ST_PC_BLOCK_JACOBI = 1, /* inverse of each node's nc x nc diagonal block */
-  DIRAC_ST_PC_SPECTRAL = 2      /* exact inverse of the operator with V replaced by
+  DIRAC_ST_PC_SPECTRAL = 2,     /* exact inverse of the operator with V replaced by
                                    the constant opts.vbar (periodic uniform mesh) */
+  DIRAC_ST_PC_LINE = 3          /* exact inverse of the operator itself for every
+                                   potential of the method (all depend on x_1 only):
+                                   time eigenbasis, DFT over x_2, x_3, periodic
+                                   block-tridiagonal solves along x_1; needs
+                                   n_t <= 2048 and workspace for nc*nc*4 factors
+                                   per node */
 };
 
 /* Problem: the spacetime box [0, len[0]] x [0, len[1]] x ... with n[0] time
@@ -232,7 +238,8 @@ int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x, void *y, v
 /* z = M^{-1} v for the preconditioner `pc` (DIRAC_ST_PC_*) in precision prec
  * (64: complex128, 32: complex64).  work: workspace of at least
  * dirac_st_workspace_bytes(A, opts, 0) bytes for opts->pc = pc (the spectral
- * preconditioner keeps its factorisation there; the call sets it up). */
+ * and line preconditioners keep their factorisations there; the call sets them
+ * up and, for the line preconditioner, synchronises the stream). */
 int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec, double vbar, const void *v,
                       void *z, void *work, size_t work_bytes, void *stream);
 
@@ -252,6 +259,17 @@ size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *opts
  * (DIRAC_ST_EBREAKDOWN if NaN/Inf appears, e.g. from b). */
 int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_opts *opts,
                    void *work, size_t work_bytes, dirac_st_stats *stats, void *stream);
+
+/* Host.  Generalised eigen-decomposition of the Galerkin time pencil used by
+ * DIRAC_ST_PC_LINE: the n_t x n_t factors of the t = 1..n_t rows and columns
+ * (Sec. 2.1 weak form with the t = 0 node moved to the right-hand side; App. A
+ * 1D element matrices) M (mass: 2h/3, h/3 in the last row, h/6 off the
+ * diagonal) and D (derivative: +-1/2 off the diagonal, 1/2 in the last
+ * diagonal entry), D W = M W diag(lam), Q = W^{-1} M^{-1}.  lam: [nt], W and Q:
+ * [nt][nt] row-major; complex128 interleaved, host memory.  ht: time step.
+ * Fails (DIRAC_ST_EINVAL with a message) if nt is out of 1..2048 or the
+ * decomposition does not pass its own residual and reconstruction checks. */
+int dirac_st_time_eigen(int32_t nt, double ht, double *lam, double *W, double *Q);
 
 /* ------------------------------------------------------------------ batches
  * Many independent systems (Alg. 1 run for several initial fields, meshes or

@@ -241,6 +241,7 @@ static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const di
     L.partial.push_back(take((size_t)L.nblk.back() * kMaxRestart * sizeof(double2)));
     L.ctrl.push_back(take(sizeof(Ctrl)));
     L.spec.push_back(o->pc == DIRAC_ST_PC_SPECTRAL ? take(spec_layout(&A[i]->prob, o->precision).total)
+                     : o->pc == DIRAC_ST_PC_LINE   ? take(line_layout(&A[i]->prob, o->precision).total)
                                                    : 0);
   }
   L.desc = take(sizeof(BSys) * nsys);
@@ -526,7 +527,7 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
       if (int rc = lists.set(hs, step, G, Gres, s)) return rc;
       const unsigned na = (unsigned)step.size();
       // Z_j = M^{-1} (sigma_j V_j)
-      if (o->pc == DIRAC_ST_PC_SPECTRAL) {
+      if (o->pc == DIRAC_ST_PC_SPECTRAL || o->pc == DIRAC_ST_PC_LINE) {
         for (int i : step) {
           const cx<T> *vj = (const cx<T> *)hs[i].V + (int64_t)j * hs[i].ldv;
           cx<T> *zj = (cx<T> *)hs[i].Z + (int64_t)j * hs[i].ldv;
@@ -629,7 +630,7 @@ static int check_batch_opts(int32_t nsys, const dirac_st_bsr *const *A, const di
   DST_CHECK(o, "opts is NULL");
   DST_CHECK(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in 1..%d", kMaxRestart);
   DST_CHECK(o->precision == 64 || o->precision == 32, "precision must be 64 or 32");
-  DST_CHECK(o->pc >= DIRAC_ST_PC_NONE && o->pc <= DIRAC_ST_PC_SPECTRAL, "unknown preconditioner %d", o->pc);
+  DST_CHECK(o->pc >= DIRAC_ST_PC_NONE && o->pc <= DIRAC_ST_PC_LINE, "unknown preconditioner %d", o->pc);
   DST_CHECK(o->rtol > 0.0 && o->max_it >= 0, "rtol must be positive and max_it >= 0");
   for (int i = 0; i < nsys; i++) {
     DST_CHECK(o->precision == 64 || A[i]->val32, "system %d: precision 32 needs val32", i);

@@ -116,6 +116,7 @@ static GmresLayout gmres_layout(const dirac_st_bsr *A, const dirac_st_opts *o, b
   off += align256(sizeof(Ctrl));
   L.spec = off;
   if (o->pc == DIRAC_ST_PC_SPECTRAL) off += spec_layout(&A->prob, o->precision).total;
+  if (o->pc == DIRAC_ST_PC_LINE) off += line_layout(&A->prob, o->precision).total;
   L.Z = off;
   if (flexible) off += vb * (size_t)o->restart;
   L.nn = off;
@@ -388,13 +389,14 @@ extern "C" int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec
   clear_error();
   if (int rc = check_bsr(A)) return rc;
   DST_CHECK(prec == 64 || prec == 32, "prec must be 64 or 32");
-  DST_CHECK(pc == DIRAC_ST_PC_BLOCK_JACOBI || pc == DIRAC_ST_PC_SPECTRAL, "pc must be 1 or 2");
+  DST_CHECK(pc >= DIRAC_ST_PC_BLOCK_JACOBI && pc <= DIRAC_ST_PC_LINE, "pc must be 1, 2 or 3");
   DST_CHECK(v && z && v != z, "v and z must be set and distinct");
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = A->nrows * A->nc;
-  if (pc == DIRAC_ST_PC_SPECTRAL) {
-    const size_t need = spec_layout(&A->prob, prec).total;
-    DST_CHECK(work != nullptr, "spectral preconditioner needs a workspace");
+  if (pc == DIRAC_ST_PC_SPECTRAL || pc == DIRAC_ST_PC_LINE) {
+    const size_t need =
+        pc == DIRAC_ST_PC_SPECTRAL ? spec_layout(&A->prob, prec).total : line_layout(&A->prob, prec).total;
+    DST_CHECK(work != nullptr, "this preconditioner needs a workspace");
     if (work_bytes < need) {
       set_error("workspace too small: %zu < %zu", work_bytes, need);
       return DIRAC_ST_ENOSPACE;
@@ -420,7 +422,7 @@ extern "C" int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x,
             kMaxRestart);
   DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
   DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
-  DST_CHECK(opts->pc >= 0 && opts->pc <= 2, "unknown preconditioner %d", opts->pc);
+  DST_CHECK(opts->pc >= DIRAC_ST_PC_NONE && opts->pc <= DIRAC_ST_PC_LINE, "unknown preconditioner %d", opts->pc);
   DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
   DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
   const size_t need = gmres_layout(A, opts, false).total;
@@ -448,7 +450,7 @@ extern "C" int dirac_st_fgmres_nn(const dirac_st_bsr *A, const void *b, void *x,
             kMaxRestart);
   DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
   DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
-  DST_CHECK(opts->pc >= 0 && opts->pc <= 2, "unknown preconditioner %d", opts->pc);
+  DST_CHECK(opts->pc >= DIRAC_ST_PC_NONE && opts->pc <= DIRAC_ST_PC_LINE, "unknown preconditioner %d", opts->pc);
   DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
   DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
   DST_CHECK(!net || A->prob.d == 2, "the network preconditioner is for 2+1D operators");

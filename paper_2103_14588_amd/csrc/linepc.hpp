@@ -1,0 +1,373 @@
+// linepc.hpp -- exact inverse of the operator for potentials that depend on
+// the first spatial coordinate only, used as a right preconditioner.
+//
+// Every potential of the method (none, the step of Sec. 4.3, its smooth
+// version) depends on x = x_1 only, so the operator is a sum of Kronecker
+// products of 1D factors:
+//   A = D_t (x) X0 + M_t (x) X1,
+//   X0 = i g0 M_x M_y M_z,
+//   X1 = i g1 D_x M_y M_z + i g2 M_x D_y M_z + i g3 M_x M_y D_z
+//        - m M_x M_y M_z - g0 P_x M_y M_z,
+// with P_x the 1D potential mass matrix (2-point Gauss per element, as in the
+// assembly).  Three exact reductions:
+//   time    D_t = M_t W diag(lambda) W^{-1}: apply Q = W^{-1} M_t^{-1} along
+//           t, solve one spatial problem per eigenvalue, apply W along t;
+//   y, z    periodic circulant factors: a DFT turns M_a into
+//           mu_a = h_a (2 + cos th_a) / 3 and D_a into i sin th_a;
+//   x       what is left per (lambda, k_y, k_z) is a periodic block
+//           tridiagonal system along x with nc x nc blocks
+//             L_i = (h/6) C_M - C_D/2 - P[i][i-1] C_P,
+//             D_i = (2h/3) C_M       - P[i][i]   C_P,
+//             U_i = (h/6) C_M + C_D/2 - P[i][i+1] C_P,
+//           C_M = i lambda mu g0 - m mu + sum_a i g_a (i sin th_a) prod_{b != a} mu_b,
+//           C_D = i mu g1, C_P = mu g0, mu = prod over the transverse axes,
+//           solved by block elimination with a border for the periodic
+//           coupling (factors precomputed once per operator, in FP64).
+// Apply: tgemm(Q) -> DFT(y, z) -> line_solve -> inverse DFT -> tgemm(W).
+#pragma once
+
+#include <cmath>
+
+#include "common.hpp"
+#include "spectral.hpp"
+
+namespace dst {
+
+// Workspace layout of the line preconditioner (bytes from its base).
+struct LineLayout {
+  size_t tw64, tw32, lam, q64, w64, q32, w32, pot, fac, lined, flag, buf, total;
+  int pm, pk;      // Q and W padded to pm x pk (multiples of 64 and 16), zero filled
+  int64_t lines;   // n_t * (spatial nodes / n_1)
+};
+
+inline LineLayout line_layout(const dirac_st_problem *p, int prec) {
+  LineLayout L{};
+  const int nt = p->n[0], nc = p->nc;
+  int64_t S = 1, twn = 0;
+  for (int a = 1; a <= p->d; a++) {
+    S *= p->n[a];
+    twn += p->n[a];
+  }
+  L.lines = (int64_t)nt * (S / p->n[1]);
+  L.pm = (nt + 63) / 64 * 64;
+  L.pk = (nt + 15) / 16 * 16;
+  const size_t cs = prec == 64 ? 16 : 8;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t r = off;
+    off += align256(b);
+    return r;
+  };
+  L.tw64 = take(twn * 16);
+  L.tw32 = take(twn * 8);
+  L.lam = take((size_t)nt * 16);
+  L.q64 = take((size_t)L.pm * L.pk * 16);
+  L.w64 = take((size_t)L.pm * L.pk * 16);
+  L.q32 = take((size_t)L.pm * L.pk * 8);
+  L.w32 = take((size_t)L.pm * L.pk * 8);
+  L.pot = take((size_t)2 * p->n[1] * 8);
+  L.fac = take((size_t)nt * S * 4 * nc * nc * cs);
+  L.lined = take((size_t)L.lines * 3 * nc * nc * cs);
+  L.flag = take(4);
+  L.buf = take((size_t)nt * S * nc * cs);
+  L.total = off;
+  return L;
+}
+
+// Y[r][c] = scale * sum_k A[r][k] X[k][c], r < nt, c < ncol: the transform
+// along time of a vector stored [t][spatial node][component] (row length
+// ncol).  A is pm x pk (zero padded).  64 x 64 output tile per workgroup,
+// 4 x 4 per thread (rows ty + 16 i, columns tx + 16 j, so that global
+// accesses are coalesced), K in steps of 16 through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void tgemm(const cx<T> *__restrict__ A, int pk,
+                                             const cx<T> *__restrict__ X, cx<T> *__restrict__ Y,
+                                             int nt, int64_t ncol, T scale) {
+  using C = cx<T>;
+  __shared__ C As[16][64];
+  __shared__ C Bs[16][64];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t col0 = (int64_t)blockIdx.x * 64;
+  const int row0 = blockIdx.y * 64;
+  C acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = mk<C>(0, 0);
+  for (int k0 = 0; k0 < nt; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int e = threadIdx.x + 256 * q;
+      const int r = e >> 4, kk = e & 15;
+      As[kk][r] = A[(int64_t)(row0 + r) * pk + k0 + kk];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int e = threadIdx.x + 256 * q;
+      const int kk = e >> 6, c = e & 63;
+      const int k = k0 + kk;
+      const int64_t col = col0 + c;
+      Bs[kk][c] = (k < nt && col < ncol) ? X[(int64_t)k * ncol + col] : mk<C>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) {
+      C a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = cfma(acc[i][j], a[i], b[j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int r = row0 + ty + 16 * i;
+    if (r >= nt) continue;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t c = col0 + tx + 16 * j;
+      if (c < ncol) Y[(int64_t)r * ncol + c] = mk<C>(acc[i][j].x * scale, acc[i][j].y * scale);
+    }
+  }
+}
+
+template <int NC>
+__device__ inline void blk_axpy(double2 *out, const double2 *a, double s, const double2 *b) {
+#pragma unroll
+  for (int q = 0; q < NC * NC; q++) out[q] = mk<double2>(a[q].x + s * b[q].x, a[q].y + s * b[q].y);
+}
+
+template <int NC>
+__device__ inline bool blk_finite(const double2 *a) {
+  bool ok = true;
+#pragma unroll
+  for (int q = 0; q < NC * NC; q++) ok = ok && isfinite(a[q].x) && isfinite(a[q].y);
+  return ok;
+}
+
+// Factors per node, layout [i_1][slot][q][line] (slot 0 G_i, 1 K_i = G_i L_i,
+// 2 E_i, 3 H_i), per line [slot][q][line] (slot 0 L_{n-1}, 1 U_{n-1} (the
+// corner coupling to node 0), 2 S^{-1}).  One thread per line; the
+// forward sweep writes F_i into the H slot, the backward sweep replaces it.
+template <typename T, int NC, int DS>
+__global__ __launch_bounds__(64) void line_setup(SpecGeom G, const double2 *__restrict__ tw,
+                                                 const double2 *__restrict__ lam,
+                                                 const double *__restrict__ pot,
+                                                 cx<T> *__restrict__ fac, cx<T> *__restrict__ lined,
+                                                 int64_t lines, int *__restrict__ flag) {
+  constexpr int B = NC * NC;
+  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (l >= lines) return;
+  const int n1 = G.n[1];
+  const int64_t nperp = G.S / n1;
+  const int tq = (int)(l / nperp);
+  int64_t rem = l - (int64_t)tq * nperp;
+  double mu[DS + 1], sn[DS + 1];
+  double mperp = 1.0;
+#pragma unroll
+  for (int a = 2; a <= DS; a++) {
+    const int k = (int)(rem % G.n[a]);
+    rem /= G.n[a];
+    const double2 w = tw[G.tw_off[a] + k];  // exp(-i th)
+    mu[a] = G.h[a] * (2.0 + w.x) / 3.0;
+    sn[a] = -w.y;
+    mperp *= mu[a];
+  }
+  const double2 lm = lam[tq];
+  const double h1 = G.h[1];
+  double2 AL[B], AD[B], AU[B], CP[B];
+#pragma unroll
+  for (int q = 0; q < B; q++) {
+    const int i = q / NC, j = q % NC;
+    const double2 g0 = G.g[0][q], g1 = G.g[1][q];
+    // i lambda mu g0
+    const double2 il = mk<double2>(-lm.y * mperp, lm.x * mperp);
+    double2 cm = cmul(il, g0);
+    if (i == j) cm.x -= G.m * mperp;
+#pragma unroll
+    for (int a = 2; a <= DS; a++) {
+      double other = 1.0;
+#pragma unroll
+      for (int b = 2; b <= DS; b++)
+        if (b != a) other *= mu[b];
+      // i g_a (i sin th_a) other = -g_a sin th_a other
+      cm.x -= G.g[a][q].x * sn[a] * other;
+      cm.y -= G.g[a][q].y * sn[a] * other;
+    }
+    const double2 cd = mk<double2>(-g1.y * mperp, g1.x * mperp);  // i mu g1
+    AL[q] = mk<double2>(h1 / 6.0 * cm.x - 0.5 * cd.x, h1 / 6.0 * cm.y - 0.5 * cd.y);
+    AU[q] = mk<double2>(h1 / 6.0 * cm.x + 0.5 * cd.x, h1 / 6.0 * cm.y + 0.5 * cd.y);
+    AD[q] = mk<double2>(2.0 * h1 / 3.0 * cm.x, 2.0 * h1 / 3.0 * cm.y);
+    CP[q] = mk<double2>(mperp * g0.x, mperp * g0.y);
+  }
+  const double *pdiag = pot, *poff = pot + n1;
+  auto fidx = [&](int i, int slot, int q) { return ((int64_t)i * 4 * B + slot * B + q) * lines + l; };
+  double2 E[B], F[B], Li[B], Di[B], Ui[B], tmp[B], Gi[B], col[B];
+#pragma unroll
+  for (int q = 0; q < B; q++) E[q] = F[q] = mk<double2>(0, 0);
+  bool ok = true;
+  for (int i = 0; i < n1 - 1; i++) {
+    blk_axpy<NC>(Li, AL, -poff[i == 0 ? n1 - 1 : i - 1], CP);
+    blk_axpy<NC>(Di, AD, -pdiag[i], CP);
+    blk_axpy<NC>(Ui, AU, -poff[i], CP);
+    // pivot D_i - L_i E_{i-1}
+    matmul_nc<NC>(Li, E, tmp);
+#pragma unroll
+    for (int q = 0; q < B; q++) tmp[q] = csub(Di[q], tmp[q]);
+    inverse_nc<NC>(tmp, Gi);
+    ok = ok && blk_finite<NC>(Gi);
+    // border column: corner L_0 in row 0, U_{n-2} in row n-2, minus L_i F_{i-1}
+    matmul_nc<NC>(Li, F, tmp);
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      double2 c = i > 0 ? mk<double2>(-tmp[q].x, -tmp[q].y) : Li[q];
+      if (i == n1 - 2) c = cadd(c, Ui[q]);
+      col[q] = c;
+    }
+    matmul_nc<NC>(Gi, col, F);
+    if (i < n1 - 2) {
+      matmul_nc<NC>(Gi, Ui, E);
+    } else {
+#pragma unroll
+      for (int q = 0; q < B; q++) E[q] = mk<double2>(0, 0);
+    }
+    if (i > 0) {
+      matmul_nc<NC>(Gi, Li, tmp);
+    } else {
+#pragma unroll
+      for (int q = 0; q < B; q++) tmp[q] = mk<double2>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      fac[fidx(i, 0, q)] = mk<cx<T>>((T)Gi[q].x, (T)Gi[q].y);
+      fac[fidx(i, 1, q)] = mk<cx<T>>((T)tmp[q].x, (T)tmp[q].y);
+      fac[fidx(i, 2, q)] = mk<cx<T>>((T)E[q].x, (T)E[q].y);
+      fac[fidx(i, 3, q)] = mk<cx<T>>((T)F[q].x, (T)F[q].y);
+    }
+  }
+  // backward: H_{n-2} = -F_{n-2}, H_i = -E_i H_{i+1} - F_i (E_i and F_i are
+  // read back at the storage precision; H is carried in FP64)
+  double2 H[B], Hl[B];
+#pragma unroll
+  for (int q = 0; q < B; q++) {
+    H[q] = mk<double2>(-F[q].x, -F[q].y);
+    Hl[q] = H[q];
+    fac[fidx(n1 - 2, 3, q)] = mk<cx<T>>((T)H[q].x, (T)H[q].y);
+  }
+  for (int i = n1 - 3; i >= 0; i--) {
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      const cx<T> e = fac[fidx(i, 2, q)], f = fac[fidx(i, 3, q)];
+      E[q] = mk<double2>((double)e.x, (double)e.y);
+      F[q] = mk<double2>((double)f.x, (double)f.y);
+    }
+    matmul_nc<NC>(E, H, tmp);
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      H[q] = mk<double2>(-tmp[q].x - F[q].x, -tmp[q].y - F[q].y);
+      fac[fidx(i, 3, q)] = mk<cx<T>>((T)H[q].x, (T)H[q].y);
+    }
+  }
+  // Schur complement of the last node: D_{n-1} + L_{n-1} H_{n-2} + U_{n-1} H_0
+  blk_axpy<NC>(Li, AL, -poff[n1 - 2], CP);
+  blk_axpy<NC>(Di, AD, -pdiag[n1 - 1], CP);
+  blk_axpy<NC>(Ui, AU, -poff[n1 - 1], CP);
+  matmul_nc<NC>(Li, Hl, tmp);
+  matmul_nc<NC>(Ui, H, col);
+#pragma unroll
+  for (int q = 0; q < B; q++) tmp[q] = cadd(Di[q], cadd(tmp[q], col[q]));
+  inverse_nc<NC>(tmp, Gi);
+  ok = ok && blk_finite<NC>(Gi);
+#pragma unroll
+  for (int q = 0; q < B; q++) {
+    lined[(0 * B + q) * lines + l] = mk<cx<T>>((T)Li[q].x, (T)Li[q].y);
+    lined[(1 * B + q) * lines + l] = mk<cx<T>>((T)Ui[q].x, (T)Ui[q].y);
+    lined[(2 * B + q) * lines + l] = mk<cx<T>>((T)Gi[q].x, (T)Gi[q].y);
+  }
+  if (!ok) atomicAdd(flag, 1);
+}
+
+template <typename T, int NC>
+__device__ inline void blk_mv(const cx<T> *__restrict__ fac, int64_t base, int64_t lines,
+                              const cx<T> *v, cx<T> *out, bool accum, bool neg) {
+#pragma unroll
+  for (int i = 0; i < NC; i++) {
+    cx<T> s = accum ? out[i] : mk<cx<T>>(0, 0);
+#pragma unroll
+    for (int j = 0; j < NC; j++) {
+      const cx<T> a = fac[base + (int64_t)(i * NC + j) * lines];
+      s = neg ? cfms(s, a, v[j]) : cfma(s, a, v[j]);
+    }
+    out[i] = s;
+  }
+}
+
+// In-place periodic block-tridiagonal solve along x, one thread per line
+// (line l holds nodes l * n1 .. l * n1 + n1 - 1, nc components each).
+template <typename T, int NC>
+__global__ __launch_bounds__(64) void line_solve(const cx<T> *__restrict__ fac,
+                                                 const cx<T> *__restrict__ lined,
+                                                 cx<T> *__restrict__ X, int n1, int64_t lines) {
+  constexpr int B = NC * NC;
+  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (l >= lines) return;
+  cx<T> *x = X + l * n1 * NC;
+  auto fb = [&](int i, int slot) { return ((int64_t)i * 4 * B + slot * B) * lines + l; };
+  cx<T> y[NC], v[NC], t[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) y[c] = mk<cx<T>>(0, 0);
+  // forward: y_i = G_i v_i - K_i y_{i-1}
+  for (int i = 0; i < n1 - 1; i++) {
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = x[i * NC + c];
+    blk_mv<T, NC>(fac, fb(i, 0), lines, v, t, false, false);
+    blk_mv<T, NC>(fac, fb(i, 1), lines, y, t, true, true);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      y[c] = t[c];
+      x[i * NC + c] = t[c];
+    }
+  }
+  // backward: a_i = y_i - E_i a_{i+1}
+  cx<T> alast[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) alast[c] = y[c];
+  for (int i = n1 - 3; i >= 0; i--) {
+#pragma unroll
+    for (int c = 0; c < NC; c++) t[c] = x[i * NC + c];
+    blk_mv<T, NC>(fac, fb(i, 2), lines, y, t, true, true);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      y[c] = t[c];
+      x[i * NC + c] = t[c];
+    }
+  }
+  // last node: S^{-1} (v_{n-1} - L_{n-1} a_{n-2} - U_{n-1} a_0)
+#pragma unroll
+  for (int c = 0; c < NC; c++) t[c] = x[(n1 - 1) * NC + c];
+  blk_mv<T, NC>(lined, 0 * B * lines + l, lines, alast, t, true, true);
+  blk_mv<T, NC>(lined, 1 * B * lines + l, lines, y, t, true, true);
+  cx<T> xl[NC];
+  blk_mv<T, NC>(lined, 2 * B * lines + l, lines, t, xl, false, false);
+#pragma unroll
+  for (int c = 0; c < NC; c++) x[(n1 - 1) * NC + c] = xl[c];
+  // x_i = a_i + H_i x_{n-1}
+  for (int i = 0; i < n1 - 1; i++) {
+#pragma unroll
+    for (int c = 0; c < NC; c++) t[c] = x[i * NC + c];
+    blk_mv<T, NC>(fac, fb(i, 3), lines, xl, t, true, false);
+#pragma unroll
+    for (int c = 0; c < NC; c++) x[i * NC + c] = t[c];
+  }
+}
+
+static __global__ void zero_i32_flag(int *f) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *f = 0;
+}
+
+}  // namespace dst

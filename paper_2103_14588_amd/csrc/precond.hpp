@@ -1,15 +1,20 @@
 // precond.hpp -- the base preconditioners M of right-preconditioned GMRES
-// (Sec. 2.2): node-block Jacobi (inverses of the diagonal nc x nc blocks) and
+// (Sec. 2.2): node-block Jacobi (inverses of the diagonal nc x nc blocks),
 // the spatial-Fourier preconditioner (the operator with the potential replaced
 // by a constant, inverted exactly: DFT over every periodic spatial axis, one
-// block-tridiagonal solve in time per Fourier mode, inverse DFT).
+// block-tridiagonal solve in time per Fourier mode, inverse DFT) and the line
+// preconditioner (exact inverse for potentials that depend on x only: time
+// eigenbasis, DFT over the transverse axes, periodic block-tridiagonal solves
+// along x).
 #pragma once
 
 #include <cmath>
 
 #include "common.hpp"
 #include "krylov.hpp"
+#include "linepc.hpp"
 #include "spectral.hpp"
+#include "time_eigen.hpp"
 
 namespace dst {
 
@@ -24,6 +29,9 @@ struct Precond {
   SpecGeom G{};
   unsigned char *spec = nullptr;
   SpecLayout SL{};
+  // line (shares G and the twiddle tables' geometry)
+  unsigned char *line = nullptr;
+  LineLayout LL{};
   // learned correction z += s N(v / s) (flexible GMRES only)
   const dirac_st_nn *nn = nullptr;
   bool nn_on = false;
@@ -94,6 +102,109 @@ static int spec_twiddles(const SpecGeom &G, unsigned char *base, const SpecLayou
   return 0;
 }
 
+// Line preconditioner set-up: time eigen-decomposition and 1D potential
+// matrix on the host (FP64), per-line factors on the device.
+static double host_potential(const dirac_st_problem *p, double x) {
+  if (p->vkind == DIRAC_ST_V_STEP) return x > p->x0 ? p->v0 : 0.0;
+  if (p->vkind == DIRAC_ST_V_SMOOTH) return 0.5 * p->v0 * (1.0 + tanh((x - p->x0) / p->lw));
+  return 0.0;
+}
+
+template <typename T>
+static int line_setup_host(Precond &P, const dirac_st_bsr *A, unsigned char *base, hipStream_t s) {
+  const dirac_st_problem *p = &A->prob;
+  DST_CHECK(p->n[0] <= kTimeEigenMax, "line preconditioner needs n_t <= %d", kTimeEigenMax);
+  P.line = base;
+  P.LL = line_layout(p, P.prec);
+  const LineLayout &L = P.LL;
+  spec_geom(p, 0.0, P.G);
+  SpecLayout tl{};
+  tl.tw64 = L.tw64;
+  tl.tw32 = L.tw32;
+  if (int rc = spec_twiddles(P.G, base, tl, s)) return rc;
+  const int nt = p->n[0], n1 = p->n[1];
+  std::vector<std::complex<double>> lam, W, Q;
+  if (int rc = time_eigen(nt, p->len[0] / nt, lam, W, Q)) return rc;
+  std::vector<double2> q64((size_t)L.pm * L.pk, mk<double2>(0, 0)), w64(q64.size(), mk<double2>(0, 0)),
+      l64(nt);
+  std::vector<float2> q32(q64.size(), mk<float2>(0, 0)), w32(q64.size(), mk<float2>(0, 0));
+  for (int r = 0; r < nt; r++) {
+    l64[r] = mk<double2>(lam[r].real(), lam[r].imag());
+    for (int c = 0; c < nt; c++) {
+      const size_t e = (size_t)r * L.pk + c;
+      const std::complex<double> qv = Q[(size_t)r * nt + c], wv = W[(size_t)r * nt + c];
+      q64[e] = mk<double2>(qv.real(), qv.imag());
+      w64[e] = mk<double2>(wv.real(), wv.imag());
+      q32[e] = mk<float2>((float)qv.real(), (float)qv.imag());
+      w32[e] = mk<float2>((float)wv.real(), (float)wv.imag());
+    }
+  }
+  // P_x: diagonal and (i, i+1) entries, 2-point Gauss on every element
+  std::vector<double> pot(2 * (size_t)n1, 0.0);
+  const double h1 = p->len[1] / n1, r3 = 0.57735026918962576451;
+  for (int e = 0; e < n1; e++)
+    for (int q = 0; q < 2; q++) {
+      const double xi = 0.5 * (1.0 + (q ? r3 : -r3));
+      const double w = 0.5 * h1 * host_potential(p, (e + xi) * h1);
+      pot[e] += w * (1.0 - xi) * (1.0 - xi);
+      pot[(e + 1) % n1] += w * xi * xi;
+      pot[n1 + e] += w * (1.0 - xi) * xi;
+    }
+  DST_HIP(hipMemcpyAsync(base + L.lam, l64.data(), l64.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  DST_HIP(hipMemcpyAsync(base + L.q64, q64.data(), q64.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  DST_HIP(hipMemcpyAsync(base + L.w64, w64.data(), w64.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  DST_HIP(hipMemcpyAsync(base + L.q32, q32.data(), q32.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+  DST_HIP(hipMemcpyAsync(base + L.w32, w32.data(), w32.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+  DST_HIP(hipMemcpyAsync(base + L.pot, pot.data(), pot.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  int *flag = (int *)(base + L.flag);
+  zero_i32_flag<<<1, 64, 0, s>>>(flag);
+  const unsigned g = (unsigned)((L.lines + 63) / 64);
+  const double2 *tw64 = (const double2 *)(base + L.tw64);
+  const double2 *lamd = (const double2 *)(base + L.lam);
+  const double *potd = (const double *)(base + L.pot);
+  cx<T> *fac = (cx<T> *)(base + L.fac), *lined = (cx<T> *)(base + L.lined);
+  if (p->d == 1)
+    line_setup<T, 2, 1><<<g, 64, 0, s>>>(P.G, tw64, lamd, potd, fac, lined, L.lines, flag);
+  else if (p->d == 2)
+    line_setup<T, 2, 2><<<g, 64, 0, s>>>(P.G, tw64, lamd, potd, fac, lined, L.lines, flag);
+  else
+    line_setup<T, 4, 3><<<g, 64, 0, s>>>(P.G, tw64, lamd, potd, fac, lined, L.lines, flag);
+  DST_LAUNCHED();
+  int bad = 0;
+  DST_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  // the host staging vectors above live on this frame: wait for every copy
+  DST_HIP(hipStreamSynchronize(s));
+  DST_CHECK(bad == 0, "line preconditioner: %d singular or non-finite line factorisations", bad);
+  return 0;
+}
+
+// One DFT pass along spatial axis a over a vector with `stride` elements
+// between consecutive nodes of that axis (direct summation in LDS tiles, or
+// radix-2 when n_a is a power of two); sc scales the output.
+template <typename T>
+static int axis_transform(const SpecGeom &G, const cx<T> *tw, const cx<T> *in, cx<T> *out, int a,
+                          int64_t stride, int sign, T sc, hipStream_t s) {
+  const int n = G.n[a];
+  const int64_t total = G.S * G.nt * G.nc;
+  const int64_t outer = total / ((int64_t)n * stride);
+  int ti = (int)(stride < 2048 / n ? stride : 2048 / n);
+  if (ti < 1) ti = 1;
+  while (stride % ti) ti--;
+  const int ntq = (int)(stride / ti);
+  const size_t sh = ((size_t)n * ti + n) * sizeof(cx<T>);
+  if ((n & (n - 1)) == 0) {
+    int logn = 0;
+    while ((1 << logn) < n) logn++;
+    fft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(in, out, n, logn, stride, ti, ntq, sign, sc,
+                                                        tw + G.tw_off[a]);
+  } else {
+    dft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(in, out, n, stride, ti, ntq, sign, sc,
+                                                        tw + G.tw_off[a]);
+  }
+  DST_LAUNCHED();
+  return 0;
+}
+
 template <typename T>
 static int pc_setup(Precond &P, const dirac_st_bsr *A, int kind, double vbar, unsigned char *spec,
                     hipStream_t s) {
@@ -104,6 +215,7 @@ static int pc_setup(Precond &P, const dirac_st_bsr *A, int kind, double vbar, un
     DST_CHECK((sizeof(T) == 8 ? A->bjinv64 : A->bjinv32) != nullptr,
               "block-Jacobi preconditioner needs bjinv%d", P.prec);
   }
+  if (kind == DIRAC_ST_PC_LINE) return line_setup_host<T>(P, A, spec, s);
   if (kind != DIRAC_ST_PC_SPECTRAL) return 0;
   P.spec = spec;
   P.SL = spec_layout(&A->prob, P.prec);
@@ -139,36 +251,17 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
   if (P.kind == DIRAC_ST_PC_SPECTRAL) {
     const SpecGeom &G = P.G;
     const cx<T> *tw = (const cx<T> *)(P.spec + (sizeof(T) == 8 ? P.SL.tw64 : P.SL.tw32));
-    const int nc = G.nc;
-    int64_t stride = nc;
-    const int64_t total = G.S * G.nt * nc;
-    // forward transforms, axis 1 first (v -> z), then in place
+    // forward transforms over every spatial axis (v -> z, then in place),
+    // block elimination along time per mode, inverse transforms
     for (int pass = 0; pass < 2; pass++) {
-      stride = nc;
+      int64_t stride = G.nc;
       for (int a = 1; a <= G.d; a++) {
-        const int n = G.n[a];
-        const int64_t outer = total / ((int64_t)n * stride);
-        int ti = (int)(stride < 2048 / n ? stride : 2048 / n);
-        if (ti < 1) ti = 1;
-        while (stride % ti) ti--;
-        const int ntq = (int)(stride / ti);
-        const size_t sh = ((size_t)n * ti + n) * sizeof(cx<T>);
         const bool first = (pass == 0 && a == 1);
         const bool last = (pass == 1 && a == G.d);
         const T sc = last ? (T)(scale / (double)G.S) : (T)1;
-        if ((n & (n - 1)) == 0) {
-          int logn = 0;
-          while ((1 << logn) < n) logn++;
-          fft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(first ? v : z, z, n, logn, stride, ti,
-                                                              ntq, pass == 0 ? -1 : 1, sc,
-                                                              tw + G.tw_off[a]);
-        } else {
-          dft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(first ? v : z, z, n, stride, ti, ntq,
-                                                              pass == 0 ? -1 : 1, sc,
-                                                              tw + G.tw_off[a]);
-        }
-        DST_LAUNCHED();
-        stride *= n;
+        if (int rc = axis_transform<T>(G, tw, first ? v : z, z, a, stride, pass == 0 ? -1 : 1, sc, s))
+          return rc;
+        stride *= G.n[a];
       }
       if (pass == 0) {
         const unsigned g = (unsigned)((G.S + 63) / 64);
@@ -183,6 +276,44 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
         DST_LAUNCHED();
       }
     }
+    return 0;
+  }
+  if (P.kind == DIRAC_ST_PC_LINE) {
+    const SpecGeom &G = P.G;
+    const LineLayout &L = P.LL;
+    const bool dbl = sizeof(T) == 8;
+    const cx<T> *tw = (const cx<T> *)(P.line + (dbl ? L.tw64 : L.tw32));
+    const cx<T> *Qm = (const cx<T> *)(P.line + (dbl ? L.q64 : L.q32));
+    const cx<T> *Wm = (const cx<T> *)(P.line + (dbl ? L.w64 : L.w32));
+    cx<T> *buf = (cx<T> *)(P.line + L.buf);
+    const int64_t ncol = G.S * G.nc;
+    const dim3 gg((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64));
+    // buf = Q v along time
+    tgemm<T><<<gg, 256, 0, s>>>(Qm, L.pk, v, buf, G.nt, ncol, (T)1);
+    DST_LAUNCHED();
+    // DFT over the transverse axes (in place)
+    int64_t stride = (int64_t)G.nc * G.n[1];
+    for (int a = 2; a <= G.d; a++) {
+      if (int rc = axis_transform<T>(G, tw, buf, buf, a, stride, -1, (T)1, s)) return rc;
+      stride *= G.n[a];
+    }
+    const unsigned gl = (unsigned)((L.lines + 63) / 64);
+    const cx<T> *fac = (const cx<T> *)(P.line + L.fac), *lined = (const cx<T> *)(P.line + L.lined);
+    if (G.nc == 2)
+      line_solve<T, 2><<<gl, 64, 0, s>>>(fac, lined, buf, G.n[1], L.lines);
+    else
+      line_solve<T, 4><<<gl, 64, 0, s>>>(fac, lined, buf, G.n[1], L.lines);
+    DST_LAUNCHED();
+    stride = (int64_t)G.nc * G.n[1];
+    const int64_t nperp = G.S / G.n[1];
+    for (int a = 2; a <= G.d; a++) {
+      const T sc = a == G.d ? (T)(1.0 / (double)nperp) : (T)1;
+      if (int rc = axis_transform<T>(G, tw, buf, buf, a, stride, 1, sc, s)) return rc;
+      stride *= G.n[a];
+    }
+    // z = scale * W buf along time
+    tgemm<T><<<gg, 256, 0, s>>>(Wm, L.pk, buf, z, G.nt, ncol, (T)scale);
+    DST_LAUNCHED();
     return 0;
   }
   set_error("no preconditioner to apply");

@@ -21,8 +21,8 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, NOT_CONVERGED, EINVAL, EHIP, EBREAKDOWN, ENOSPACE = 0, 1, -1, -2, -3, -4
 V_NONE, V_STEP, V_SMOOTH = 0, 1, 2
-PC_NONE, PC_BLOCK_JACOBI, PC_SPECTRAL = 0, 1, 2
-PC_NAMES = {"none": PC_NONE, "bj": PC_BLOCK_JACOBI, "spectral": PC_SPECTRAL}
+PC_NONE, PC_BLOCK_JACOBI, PC_SPECTRAL, PC_LINE = 0, 1, 2, 3
+PC_NAMES = {"none": PC_NONE, "bj": PC_BLOCK_JACOBI, "spectral": PC_SPECTRAL, "line": PC_LINE}
 
 
 class Problem(C.Structure):
@@ -89,6 +89,7 @@ _lib.dirac_st_spmv_batched_workspace_bytes.argtypes = [_i32]
 _lib.dirac_st_spmv_batched_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_spmv_batched.argtypes = [_i32, C.POINTER(_BSRP), _i32, C.POINTER(_vp), C.POINTER(_vp), _i32,
                                        _vp, C.c_size_t, _vp]
+_lib.dirac_st_time_eigen.argtypes = [_i32, C.c_double, _vp, _vp, _vp]
 _lib.dirac_st_batched_set_lanes.argtypes = [_i32, _i32, _i32]
 _lib.dirac_st_batched_lanes.argtypes = [_i32, _i32, _i64]
 _lib.dirac_st_batched_lanes.restype = _i32
@@ -99,7 +100,7 @@ EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_
            "dirac_st_nn_forward", "dirac_st_nn_backward", "dirac_st_nn_train_step",
            "dirac_st_fgmres_nn", "dirac_st_batched_workspace_bytes", "dirac_st_fgmres_batched",
            "dirac_st_spmv_batched_workspace_bytes", "dirac_st_spmv_batched",
-           "dirac_st_batched_set_lanes", "dirac_st_batched_lanes"]
+           "dirac_st_batched_set_lanes", "dirac_st_batched_lanes", "dirac_st_time_eigen"]
 
 
 class DiracError(RuntimeError):
@@ -228,7 +229,7 @@ def pc_apply(op: Operator, v: torch.Tensor, pc="spectral", vbar=0.0, z=None, wor
     o = Opts(restart=1, max_it=1, pc=kind, precision=prec, max_cycles=0, rtol=1e-8, inner_rtol=0.0,
              vbar=vbar)
     nbytes = 0
-    if kind == PC_SPECTRAL:
+    if kind in (PC_SPECTRAL, PC_LINE):
         nbytes = _lib.dirac_st_workspace_bytes(C.byref(op.bsr), C.byref(o), 0)
         if work is None or work.numel() < nbytes:
             work = torch.empty(nbytes, dtype=torch.uint8, device=v.device)
@@ -430,3 +431,13 @@ def batched_set_lanes(nc: int, prec: int, lanes: int) -> None:
 def batched_lanes(nc: int, prec: int, rows: int) -> int:
     """Lanes the batched solver uses for a batch of `rows` block rows (0: not tuned yet)."""
     return int(_lib.dirac_st_batched_lanes(nc, prec, rows))
+
+
+def time_eigen(nt: int, ht: float):
+    """dirac_st_time_eigen (host): (lam [nt], W [nt, nt], Q [nt, nt]) complex128 numpy arrays."""
+    import numpy as np
+    lam = np.zeros(nt, np.complex128)
+    W = np.zeros((nt, nt), np.complex128)
+    Q = np.zeros((nt, nt), np.complex128)
+    _check(_lib.dirac_st_time_eigen(nt, ht, lam.ctypes.data, W.ctypes.data, Q.ctypes.data))
+    return lam, W, Q
