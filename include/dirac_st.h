@@ -275,7 +275,8 @@ int dirac_st_time_eigen(int32_t nt, double ht, double *lam, double *W, double *Q
  * Many independent systems (Alg. 1 run for several initial fields, meshes or
  * potentials) solved together: every phase of an Arnoldi step is one launch
  * for the whole batch, its workgroups spread over the systems' tiles.
- * All systems of a batch must have the same block size nc (same d). */
+ * All systems of a batch must have the same block size nc; a batched solve
+ * also needs the same dimension d for every system. */
 
 /* Maximum number of systems in one batched call. */
 #define DIRAC_ST_MAX_BATCH 1024

@@ -44,6 +44,17 @@ struct BSys {
   double2 *partial;  // [64][nblk]
   Ctrl *ctrl;
   int nc, k;     // block size; steps of the current cycle (set before updates)
+  int64_t lt[4]; // line preconditioner workgroups: time transform, axis 2, axis 3, line solve
+};
+
+// Line preconditioner of one system (device copy; pointers at the working precision).
+struct LineJob {
+  const void *Q, *W, *F[4], *Fi[4];
+  void *b1, *b2;
+  const void *fac, *lined;
+  int pk, pm, dpk[4], dpm[4];
+  int d, nc, nt, n[4];
+  int64_t S, lines;
 };
 
 constexpr int kMaxBatch = DIRAC_ST_MAX_BATCH;
@@ -69,8 +80,13 @@ __device__ inline int find_sys(const WorkList &L, int64_t &local) {
     if (so[mid] <= bid) lo = mid;
     else hi = mid;
   }
-  local = bid - so[lo];
-  return (int)L.act[lo];
+  // every lane holds the same values: make that visible to the compiler so
+  // the descriptor fields and everything derived from them stay scalar
+  const int64_t loc = bid - so[lo];
+  const int lo32 = __builtin_amdgcn_readfirstlane((int)(uint32_t)(loc & 0xffffffff));
+  const int hi32 = __builtin_amdgcn_readfirstlane((int)(loc >> 32));
+  local = ((int64_t)hi32 << 32) | (uint32_t)lo32;
+  return __builtin_amdgcn_readfirstlane((int)L.act[lo]);
 }
 
 // ------------------------------------------------------------ grouped kernels
@@ -100,14 +116,14 @@ __global__ __launch_bounds__(256) void g_cgs(const BSys *__restrict__ S, WorkLis
                            s.partial, s.n);
 }
 
-// partial[0][b] = |r64|^2 (src 0) or |b|^2 (src 1) over the block
+// partial[0][b] = |r64|^2 (src 0), |b|^2 (src 1) or |x|^2 (src 2) over the block
 __global__ __launch_bounds__(256) void g_norm(const BSys *__restrict__ S, WorkList L, int src) {
   __shared__ double red[4];
   int64_t blk;
   const BSys &s = S[find_sys(L, blk)];
   const int64_t e = blk * 256 + threadIdx.x;
   double v = 0.0;
-  if (e < s.n) v = cabs2(src == 0 ? s.r64[e] : s.b[e]);
+  if (e < s.n) v = cabs2(src == 0 ? s.r64[e] : src == 1 ? s.b[e] : s.x[e]);
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -169,6 +185,106 @@ __global__ __launch_bounds__(256) void g_pc_local(const BSys *__restrict__ S, Wo
   z[e] = mk<cx<T>>(acc.x * sg, acc.y * sg);
 }
 
+// One transform of the line preconditioner for every listed system.
+// axis 0: along time (Q, or W when dst == 3); axis a >= 2: transverse DFT
+// (inverse if inv).  src/dst: 0 V_j, 1 b1, 2 b2, 3 Z_j.  The W transform
+// scales by sigma_j (the stored V_j is sigma_j^{-1} times the basis vector).
+// grid (x: tiles of the largest system, y: active systems).  AXIS 0: along
+// time (Q, or sigma_j W when DST == 3); AXIS 2, 3: transverse DFT (inverse if
+// INV).  SRC/DST: 0 V_j, 1 b1, 2 b2, 3 Z_j.
+template <typename T, int AXIS, bool INV, int SRC, int DST>
+__global__ __launch_bounds__(256) void g_line_gemm(const BSys *__restrict__ S, const LineJob *__restrict__ J,
+                                                   const int64_t *__restrict__ act, int j) {
+  const int sys = (int)act[blockIdx.y];
+  const BSys &s = S[sys];
+  if ((int64_t)blockIdx.x >= s.lt[AXIS == 0 ? 0 : AXIS - 1]) return;
+  const LineJob &q = J[sys];
+  using C = cx<T>;
+  const C *A;
+  int pk, pm, n;
+  int64_t cols, batches = 1;
+  if (AXIS == 0) {
+    A = (const C *)(DST == 3 ? q.W : q.Q);
+    pk = q.pk;
+    pm = q.pm;
+    n = q.nt;
+    cols = q.S * q.nc;
+  } else {
+    A = (const C *)(INV ? q.Fi[AXIS] : q.F[AXIS]);
+    pk = q.dpk[AXIS];
+    pm = q.dpm[AXIS];
+    n = q.n[AXIS];
+    cols = q.nc;
+    for (int b = 1; b < AXIS; b++) cols *= q.n[b];
+  }
+  (void)batches;
+  // 32-bit index arithmetic: every count here is below 2^31 (grid limit)
+  const unsigned nct = (unsigned)((cols + 63) / 64), nrt = (unsigned)(pm / 64), t32 = blockIdx.x;
+  const unsigned ct = t32 % nct, rt = (t32 / nct) % nrt, bt = t32 / (nct * nrt);
+  const C *X = SRC == 0 ? (const C *)s.V + (int64_t)j * s.ldv : (const C *)(SRC == 1 ? q.b1 : q.b2);
+  C *Y = DST == 3 ? (C *)s.Z + (int64_t)j * s.ldv : (C *)(DST == 1 ? q.b1 : q.b2);
+  const int64_t boff = (int64_t)bt * n * cols;
+  const T scale = DST == 3 ? (T)s.ctrl->sigma[j] : (T)1;
+  tgemm_tile<T>(A, pk, X + boff, Y + boff, n, cols, (int)rt * 64, (int64_t)ct * 64, scale);
+}
+
+// launches one transform of the line preconditioner (template dispatch)
+template <typename T>
+static void launch_line_gemm(int axis, bool inv, int src, int dst, dim3 grid, const BSys *S, const LineJob *J,
+                             const int64_t *act, int j, hipStream_t st) {
+  if (axis == 0) {
+    if (dst == 3) {
+      if (src == 1) g_line_gemm<T, 0, false, 1, 3><<<grid, 256, 0, st>>>(S, J, act, j);
+      else g_line_gemm<T, 0, false, 2, 3><<<grid, 256, 0, st>>>(S, J, act, j);
+    } else {
+      g_line_gemm<T, 0, false, 0, 1><<<grid, 256, 0, st>>>(S, J, act, j);
+    }
+    return;
+  }
+#define DST_LG(AX)                                                                           \
+  if (axis == AX) {                                                                          \
+    if (inv) {                                                                               \
+      if (src == 1) g_line_gemm<T, AX, true, 1, 2><<<grid, 256, 0, st>>>(S, J, act, j);       \
+      else g_line_gemm<T, AX, true, 2, 1><<<grid, 256, 0, st>>>(S, J, act, j);               \
+    } else {                                                                                 \
+      if (src == 1) g_line_gemm<T, AX, false, 1, 2><<<grid, 256, 0, st>>>(S, J, act, j);      \
+      else g_line_gemm<T, AX, false, 2, 1><<<grid, 256, 0, st>>>(S, J, act, j);              \
+    }                                                                                        \
+  }
+  DST_LG(2)
+  DST_LG(3)
+#undef DST_LG
+}
+
+// Factorisation of the line preconditioner of every system in one launch.
+struct LineSetupJob {
+  SpecGeom G;
+  const double2 *tw, *lam;
+  const double *pot;
+  void *fac, *lined;
+  int64_t lines;
+  int *flag;
+};
+
+template <typename T, int NC, int DS>
+__global__ __launch_bounds__(64) void g_line_setup(const LineSetupJob *__restrict__ J, WorkList L) {
+  int64_t tile;
+  const LineSetupJob &q = J[find_sys(L, tile)];
+  const int64_t l = tile * 64 + threadIdx.x;
+  if (l < q.lines)
+    line_setup_one<T, NC, DS>(q.G, q.tw, q.lam, q.pot, (cx<T> *)q.fac, (cx<T> *)q.lined, q.lines, q.flag, l);
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(64) void g_line_solve(const LineJob *__restrict__ J, WorkList L, int buf) {
+  int64_t tile;
+  const LineJob &q = J[find_sys(L, tile)];
+  const int64_t l = tile * 64 + threadIdx.x;
+  if (l < q.lines)
+    line_solve_one<T, NC>((const cx<T> *)q.fac, (const cx<T> *)q.lined, (cx<T> *)(buf == 1 ? q.b1 : q.b2),
+                          q.n[1], q.lines, l);
+}
+
 // x += sum_{i < k} Z_i coef_i (FP64 accumulation)
 template <typename T>
 __global__ __launch_bounds__(256) void g_update(const BSys *__restrict__ S, WorkList L) {
@@ -181,6 +297,14 @@ __global__ __launch_bounds__(256) void g_update(const BSys *__restrict__ S, Work
   const double2 *coef = s.ctrl->coef;
   for (int i = 0; i < s.k; i++) acc = cfma(acc, to64(Z[(int64_t)i * s.ldv + e]), coef[i]);
   s.x[e] = acc;
+}
+
+// r64 = b (the residual of the zero initial guess)
+__global__ __launch_bounds__(256) void g_copy_b(const BSys *__restrict__ S, WorkList L) {
+  int64_t blk;
+  const BSys &s = S[find_sys(L, blk)];
+  const int64_t e = blk * 256 + threadIdx.x;
+  if (e < s.n) s.r64[e] = s.b[e];
 }
 
 // which = 0: Z_0 = 0 (working precision); which = 1: x = 0
@@ -214,10 +338,14 @@ __global__ void g_zero_ctrl(const BSys *__restrict__ S) {
 }
 
 // ------------------------------------------------------------ host side
+// work-list arrays: active systems, SpMV tiles, residual SpMV tiles, vector
+// blocks, and the four line-preconditioner phases
+constexpr int kListArrays = 8;
+
 struct BatchLayout {
   std::vector<size_t> V, Z, r64, partial, ctrl, spec;
   std::vector<int64_t> ldv, nblk;
-  size_t desc, lists, gather, total;
+  size_t desc, jobs, sjobs, lists, gather, total;
 };
 
 static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const dirac_st_opts *o) {
@@ -245,7 +373,9 @@ static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const di
                                                    : 0);
   }
   L.desc = take(sizeof(BSys) * nsys);
-  L.lists = take(sizeof(int64_t) * 4 * (nsys + 1));
+  L.jobs = take(sizeof(LineJob) * nsys);
+  L.sjobs = take(sizeof(LineSetupJob) * nsys);
+  L.lists = take(sizeof(int64_t) * kListArrays * (nsys + 1));
   L.gather = take(sizeof(double) * 5 * nsys);
   L.total = off;
   return L;
@@ -259,8 +389,9 @@ struct Lists {
   int cap = 0;
   std::vector<int> cur;
   int G = -1, Gres = -1;
-  WorkList w{}, r{}, v{};
-  unsigned nw = 0, nr = 0, nv = 0;
+  WorkList w{}, r{}, v{}, ph[4]{};
+  unsigned nw = 0, nr = 0, nv = 0, nph[4] = {0, 0, 0, 0};
+  int64_t maxph[4] = {0, 0, 0, 0};  // largest per-system count of each phase
   std::vector<int64_t> host;
 
   int set(const std::vector<BSys> &hs, const std::vector<int> &act, int g, int gres, hipStream_t s) {
@@ -269,8 +400,9 @@ struct Lists {
     G = g;
     Gres = gres;
     const int na = (int)act.size();
-    host.assign(4 * (size_t)(cap + 1), 0);
-    int64_t *ha = host.data(), *hw = ha + (cap + 1), *hr = hw + (cap + 1), *hv = hr + (cap + 1);
+    const size_t c1 = (size_t)cap + 1;
+    host.assign(kListArrays * c1, 0);
+    int64_t *ha = host.data(), *hw = ha + c1, *hr = hw + c1, *hv = hr + c1, *hp = hv + c1;
     const int64_t rw = 256 / g, rr = 256 / gres;
     for (int a = 0; a < na; a++) {
       const BSys &q = hs[act[a]];
@@ -278,14 +410,25 @@ struct Lists {
       hw[a + 1] = hw[a] + (q.nrows + rw - 1) / rw;
       hr[a + 1] = hr[a] + (q.nrows + rr - 1) / rr;
       hv[a + 1] = hv[a] + q.nblk;
+      for (int k = 0; k < 4; k++) hp[k * c1 + a + 1] = hp[k * c1 + a] + q.lt[k];
     }
-    DST_CHECK(hw[na] < (int64_t(1) << 31) && hv[na] < (int64_t(1) << 31), "batch too large for one grid");
+    for (int k = 0; k < 4; k++) {
+      maxph[k] = 0;
+      for (int a = 0; a < na; a++) maxph[k] = std::max(maxph[k], hs[act[a]].lt[k]);
+    }
+    bool fits = hw[na] < (int64_t(1) << 31) && hr[na] < (int64_t(1) << 31) && hv[na] < (int64_t(1) << 31);
+    for (int k = 0; k < 4; k++) fits = fits && hp[k * c1 + na] < (int64_t(1) << 31);
+    DST_CHECK(fits, "batch too large for one grid");
     nw = (unsigned)hw[na];
     nr = (unsigned)hr[na];
     nv = (unsigned)hv[na];
-    w = {dev, dev + (cap + 1), na};
-    r = {dev, dev + 2 * (cap + 1), na};
-    v = {dev, dev + 3 * (cap + 1), na};
+    w = {dev, dev + c1, na};
+    r = {dev, dev + 2 * c1, na};
+    v = {dev, dev + 3 * c1, na};
+    for (int k = 0; k < 4; k++) {
+      nph[k] = (unsigned)hp[k * c1 + na];
+      ph[k] = {dev, dev + (4 + k) * c1, na};
+    }
     DST_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     // the host staging vector is rewritten by the next call: wait for the copy
     DST_HIP(hipStreamSynchronize(s));
@@ -420,6 +563,11 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
   std::vector<BSys> hs(nsys);
   std::vector<Precond> pcs(nsys);
   BSys *dS = (BSys *)(work + BL.desc);
+  LineJob *dJ = (LineJob *)(work + BL.jobs);
+  LineSetupJob *dSJ = (LineSetupJob *)(work + BL.sjobs);
+  std::vector<LineJob> jobs(nsys);
+  std::vector<LineSetupJob> sjobs(o->pc == DIRAC_ST_PC_LINE ? nsys : 0);
+  std::vector<LineStaging> staging(o->pc == DIRAC_ST_PC_LINE ? nsys : 0);
   double *dGat = (double *)(work + BL.gather);
   Lists lists;
   lists.dev = (int64_t *)(work + BL.lists);
@@ -435,10 +583,65 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
     q.b = (const double2 *)b[i];
     q.partial = (double2 *)(work + BL.partial[i]);
     q.ctrl = (Ctrl *)(work + BL.ctrl[i]);
-    if (o->pc != DIRAC_ST_PC_NONE) {
+    if (o->pc == DIRAC_ST_PC_LINE) {
+      // host part now; the factorisations run grouped once every system is prepared
+      pcs[i].kind = DIRAC_ST_PC_LINE;
+      pcs[i].prec = sizeof(T) == 8 ? 64 : 32;
+      pcs[i].A = A[i];
+      if (int rc = line_prepare<T>(pcs[i], A[i], work + BL.spec[i], staging[i], s)) return rc;
+    } else if (o->pc != DIRAC_ST_PC_NONE) {
       const double vbar = o->vbar >= 0.0 ? o->vbar : 0.5 * A[i]->prob.v0;
       if (int rc = pc_setup<T>(pcs[i], A[i], o->pc, vbar, work + BL.spec[i], s)) return rc;
     }
+    for (int k = 0; k < 4; k++) q.lt[k] = 0;
+    if (o->pc == DIRAC_ST_PC_LINE) {
+      const LineLayout &LL = pcs[i].LL;
+      const dirac_st_problem &pr = A[i]->prob;
+      unsigned char *lb = pcs[i].line;
+      const bool dbl = sizeof(T) == 8;
+      LineJob &jb = jobs[i];
+      jb = LineJob{};
+      jb.Q = lb + (dbl ? LL.q64 : LL.q32);
+      jb.W = lb + (dbl ? LL.w64 : LL.w32);
+      jb.b1 = lb + LL.buf;
+      jb.b2 = lb + LL.buf2;
+      jb.fac = lb + LL.fac;
+      jb.lined = lb + LL.lined;
+      jb.pk = LL.pk;
+      jb.pm = LL.pm;
+      jb.d = pr.d;
+      jb.nc = pr.nc;
+      jb.nt = pr.n[0];
+      jb.S = q.nrows / pr.n[0];
+      jb.lines = LL.lines;
+      for (int a = 0; a < 4; a++) jb.n[a] = a <= pr.d ? pr.n[a] : 1;
+      const int64_t ncol = jb.S * pr.nc;
+      q.lt[0] = (ncol + 63) / 64 * (LL.pm / 64);
+      for (int a = 2; a <= pr.d; a++) {
+        jb.F[a] = lb + (dbl ? LL.f64[a] : LL.f32[a]);
+        jb.Fi[a] = lb + (dbl ? LL.fi64[a] : LL.fi32[a]);
+        jb.dpk[a] = LL.dpk[a];
+        jb.dpm[a] = LL.dpm[a];
+        int64_t cols = pr.nc, batches = pr.n[0];
+        for (int b = 1; b < a; b++) cols *= pr.n[b];
+        for (int b = a + 1; b <= pr.d; b++) batches *= pr.n[b];
+        q.lt[a - 1] = batches * ((cols + 63) / 64) * (LL.dpm[a] / 64);
+      }
+      q.lt[3] = (LL.lines + 63) / 64;
+      LineSetupJob &sj = sjobs[i];
+      sj.G = pcs[i].G;
+      sj.tw = (const double2 *)(lb + LL.tw64);
+      sj.lam = (const double2 *)(lb + LL.lam);
+      sj.pot = (const double *)(lb + LL.pot);
+      sj.fac = lb + LL.fac;
+      sj.lined = lb + LL.lined;
+      sj.lines = LL.lines;
+      sj.flag = (int *)(lb + LL.flag);
+    }
+  }
+  if (o->pc == DIRAC_ST_PC_LINE) {
+    DST_HIP(hipMemcpyAsync(dJ, jobs.data(), sizeof(LineJob) * nsys, hipMemcpyHostToDevice, s));
+    DST_HIP(hipMemcpyAsync(dSJ, sjobs.data(), sizeof(LineSetupJob) * nsys, hipMemcpyHostToDevice, s));
   }
   auto upload_desc = [&]() -> int {
     DST_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
@@ -465,19 +668,39 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
     DST_HIP(hipStreamSynchronize(s));
     return 0;
   };
-  // residual norms of the listed systems into rb[5a + 4]: r64 = b - A x (resid) or ||b||
-  auto norms = [&](bool resid) -> int {
+  // norms of the listed systems into rb[5a + 4] (and ctrl->dots_norm2):
+  // src 0: r64 = b - A x, then ||r64||; src 1: ||b||; src 2: ||x||
+  auto norms = [&](int src) -> int {
     const unsigned na = (unsigned)lists.cur.size();
-    if (resid) DST_HIP(nc == 2 ? (launch_g_spmv<double, 2, 1>(Gres, dS, lists.r, lists.nr, 0, s))
-                               : (launch_g_spmv<double, 4, 1>(Gres, dS, lists.r, lists.nr, 0, s)));
-    g_norm<<<lists.nv, 256, 0, s>>>(dS, lists.v, resid ? 0 : 1);
+    if (src == 0) DST_HIP(nc == 2 ? (launch_g_spmv<double, 2, 1>(Gres, dS, lists.r, lists.nr, 0, s))
+                                  : (launch_g_spmv<double, 4, 1>(Gres, dS, lists.r, lists.nr, 0, s)));
+    g_norm<<<lists.nv, 256, 0, s>>>(dS, lists.v, src);
     g_reduce<<<dim3(1, na), 256, 0, s>>>(dS, lists.w.act, 1, 0);
     DST_LAUNCHED();
     return gather((int)na);
   };
 
   if (int rc = lists.set(hs, all, G, Gres, s)) return rc;
-  if (int rc = norms(false)) return rc;
+  if (o->pc == DIRAC_ST_PC_LINE) {
+    const int d = A[0]->prob.d;
+    if (d == 1) g_line_setup<T, 2, 1><<<lists.nph[3], 64, 0, s>>>(dSJ, lists.ph[3]);
+    else if (d == 2) g_line_setup<T, 2, 2><<<lists.nph[3], 64, 0, s>>>(dSJ, lists.ph[3]);
+    else g_line_setup<T, 4, 3><<<lists.nph[3], 64, 0, s>>>(dSJ, lists.ph[3]);
+    DST_LAUNCHED();
+    std::vector<int> bad(nsys, 0);
+    for (int i = 0; i < nsys; i++)
+      DST_HIP(hipMemcpyAsync(&bad[i], sjobs[i].flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DST_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nsys; i++)
+      DST_CHECK(bad[i] == 0, "system %d: line preconditioner has %d singular line factorisations", i, bad[i]);
+    staging.clear();
+  }
+  // a zero initial guess needs no first SpMV: its residual is b.  The norm
+  // of b is taken last so that ctrl->dots_norm2 holds ||b||^2 afterwards.
+  if (int rc = norms(2)) return rc;
+  std::vector<char> xzero(nsys);
+  for (int i = 0; i < nsys; i++) xzero[i] = rb[5 * i + 4] == 0.0;
+  if (int rc = norms(1)) return rc;
   std::vector<int> active, zero_b;
   for (int i = 0; i < nsys; i++) {
     bnorm[i] = sqrt(rb[5 * i + 4]);
@@ -496,10 +719,20 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
   }
 
   std::vector<double> sigma(nsys, 1.0), rstart(nsys, 0.0);
+  bool first = true;
   while (!active.empty()) {
     // FP64 true residuals decide convergence and restart
     if (int rc = lists.set(hs, active, G, Gres, s)) return rc;
-    if (int rc = norms(true)) return rc;
+    bool all_zero = first;
+    for (int i : active) all_zero = all_zero && xzero[i];
+    if (all_zero) {
+      g_copy_b<<<lists.nv, 256, 0, s>>>(dS, lists.v);
+      DST_LAUNCHED();
+      for (size_t a = 0; a < active.size(); a++) rb[5 * a + 4] = bnorm[active[a]] * bnorm[active[a]];
+    } else if (int rc = norms(0)) {
+      return rc;
+    }
+    first = false;
     std::vector<int> cyc;
     for (size_t a = 0; a < active.size(); a++) {
       const int i = active[a];
@@ -527,7 +760,25 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
       if (int rc = lists.set(hs, step, G, Gres, s)) return rc;
       const unsigned na = (unsigned)step.size();
       // Z_j = M^{-1} (sigma_j V_j)
-      if (o->pc == DIRAC_ST_PC_SPECTRAL || o->pc == DIRAC_ST_PC_LINE) {
+      if (o->pc == DIRAC_ST_PC_LINE) {
+        // Q along time, transverse DFTs, line solves, inverse DFTs, sigma_j W
+        const int d = A[0]->prob.d;
+        const int64_t *act = lists.w.act;
+        auto grid = [&](int k) { return dim3((unsigned)lists.maxph[k], na); };
+        launch_line_gemm<T>(0, false, 0, 1, grid(0), dS, dJ, act, j, s);
+        int cur = 1, oth = 2;
+        for (int a = d; a >= 2; a--) {
+          launch_line_gemm<T>(a, false, cur, oth, grid(a - 1), dS, dJ, act, j, s);
+          std::swap(cur, oth);
+        }
+        if (nc == 2) g_line_solve<T, 2><<<lists.nph[3], 64, 0, s>>>(dJ, lists.ph[3], cur);
+        else g_line_solve<T, 4><<<lists.nph[3], 64, 0, s>>>(dJ, lists.ph[3], cur);
+        for (int a = 2; a <= d; a++) {
+          launch_line_gemm<T>(a, true, cur, oth, grid(a - 1), dS, dJ, act, j, s);
+          std::swap(cur, oth);
+        }
+        launch_line_gemm<T>(0, false, cur, 3, grid(0), dS, dJ, act, j, s);
+      } else if (o->pc == DIRAC_ST_PC_SPECTRAL) {
         for (int i : step) {
           const cx<T> *vj = (const cx<T> *)hs[i].V + (int64_t)j * hs[i].ldv;
           cx<T> *zj = (cx<T> *)hs[i].Z + (int64_t)j * hs[i].ldv;
@@ -633,6 +884,7 @@ static int check_batch_opts(int32_t nsys, const dirac_st_bsr *const *A, const di
   DST_CHECK(o->pc >= DIRAC_ST_PC_NONE && o->pc <= DIRAC_ST_PC_LINE, "unknown preconditioner %d", o->pc);
   DST_CHECK(o->rtol > 0.0 && o->max_it >= 0, "rtol must be positive and max_it >= 0");
   for (int i = 0; i < nsys; i++) {
+    DST_CHECK(A[i]->prob.d == A[0]->prob.d, "all systems of a batched solve must have the same dimension");
     DST_CHECK(o->precision == 64 || A[i]->val32, "system %d: precision 32 needs val32", i);
     if (o->pc == DIRAC_ST_PC_BLOCK_JACOBI)
       DST_CHECK(o->precision == 64 ? A[i]->bjinv64 != nullptr : A[i]->bjinv32 != nullptr,
@@ -674,7 +926,7 @@ extern "C" size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys) {
     set_error("batch size must be in 1..%d", kMaxBatch);
     return 0;
   }
-  return align256(sizeof(BSys) * nsys) + align256(sizeof(int64_t) * 4 * (nsys + 1));
+  return align256(sizeof(BSys) * nsys) + align256(sizeof(int64_t) * kListArrays * (nsys + 1));
 }
 
 extern "C" int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A, int32_t prec,

@@ -203,7 +203,10 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   S.fallback = 0;
   double relres_prev = -1.0;
 
-  double bnorm = 0.0;
+  // a zero initial guess needs no first SpMV: its residual is b
+  double xnorm = 0.0, bnorm = 0.0;
+  if (int rc = read_norm(x, xnorm)) return rc;
+  bool x_zero = xnorm == 0.0;
   if (int rc = read_norm(b, bnorm)) return rc;
   if (!std::isfinite(bnorm)) {
     set_error("right-hand side contains NaN or Inf");
@@ -220,10 +223,16 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   double2 *rbuf = sizeof(T) == 8 ? (double2 *)V : r64;
   for (;;) {
     // true residual in FP64
-    DST_HIP(launch_spmv<double>(nc, A->nrows, A->row_ptr, A->col_idx, A->val64, x, b, rbuf, 1.0,
-                                true, s));
     double rn = 0.0;
-    if (int rc = read_norm(rbuf, rn)) return rc;
+    if (x_zero) {
+      DST_HIP(hipMemcpyAsync(rbuf, b, (size_t)N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      rn = bnorm;
+      x_zero = false;
+    } else {
+      DST_HIP(launch_spmv<double>(nc, A->nrows, A->row_ptr, A->col_idx, A->val64, x, b, rbuf, 1.0,
+                                  true, s));
+      if (int rc = read_norm(rbuf, rn)) return rc;
+    }
     S.relres = rn / bnorm;
     if (!std::isfinite(rn)) {
       set_error("NaN or Inf in the residual");

@@ -71,7 +71,7 @@ __device__ inline S wave_sum(S v) {
 enum PassMode { DOTS = 0, UPDOTS = 1, UPNORM = 2, UPDATE = 3 };
 
 template <typename T, int MAXK, int MODE>
-__device__ inline void cgs_block(int64_t blk, int64_t nblk, const cx<T> *__restrict__ V, int64_t ldv, int jp1,
+__device__ __forceinline__ void cgs_block(int64_t blk, int64_t nblk, const cx<T> *__restrict__ V, int64_t ldv, int jp1,
                                                  cx<T> *__restrict__ w,
                                                  const double2 *__restrict__ coef,
                                                  double2 *__restrict__ partial, int64_t n) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int
 // Layout: partial[k * nblk + b], contiguous per coefficient.
 // what: 0 -> Gram-Schmidt coefficients into dst (h1 or h2) and coef = sigma_k h_k
 //       1 -> norm^2 into ctrl->dots_norm2
-__device__ inline void reduce_coef(int k, const double2 *__restrict__ partial, int64_t nblk,
+__device__ __forceinline__ void reduce_coef(int k, const double2 *__restrict__ partial, int64_t nblk,
                                    Ctrl *__restrict__ ctrl, int what, int which) {
   __shared__ double sx[4], sy[4];
   double ax = 0.0, ay = 0.0;

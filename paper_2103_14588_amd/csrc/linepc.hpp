@@ -35,7 +35,11 @@ namespace dst {
 
 // Workspace layout of the line preconditioner (bytes from its base).
 struct LineLayout {
-  size_t tw64, tw32, lam, q64, w64, q32, w32, pot, fac, lined, flag, buf, total;
+  size_t tw64, tw32, lam, q64, w64, q32, w32, pot, fac, lined, flag, buf, buf2, total;
+  // DFT matrices of the transverse axes a = 2, 3 (forward F, inverse F^{-1}),
+  // padded to dpm[a] x dpk[a]
+  size_t f64[4], fi64[4], f32[4], fi32[4];
+  int dpm[4], dpk[4];
   int pm, pk;      // Q and W padded to pm x pk (multiples of 64 and 16), zero filled
   int64_t lines;   // n_t * (spatial nodes / n_1)
 };
@@ -70,31 +74,47 @@ inline LineLayout line_layout(const dirac_st_problem *p, int prec) {
   L.lined = take((size_t)L.lines * 3 * nc * nc * cs);
   L.flag = take(4);
   L.buf = take((size_t)nt * S * nc * cs);
+  L.buf2 = p->d >= 2 ? take((size_t)nt * S * nc * cs) : L.buf;
+  for (int a = 0; a < 4; a++) {
+    L.f64[a] = L.fi64[a] = L.f32[a] = L.fi32[a] = 0;
+    L.dpm[a] = L.dpk[a] = 0;
+  }
+  for (int a = 2; a <= p->d; a++) {
+    const int n = p->n[a];
+    L.dpm[a] = (n + 63) / 64 * 64;
+    L.dpk[a] = (n + 15) / 16 * 16;
+    const size_t e = (size_t)L.dpm[a] * L.dpk[a];
+    L.f64[a] = take(e * 16);
+    L.fi64[a] = take(e * 16);
+    L.f32[a] = take(e * 8);
+    L.fi32[a] = take(e * 8);
+  }
   L.total = off;
   return L;
 }
 
-// Y[r][c] = scale * sum_k A[r][k] X[k][c], r < nt, c < ncol: the transform
-// along time of a vector stored [t][spatial node][component] (row length
-// ncol).  A is pm x pk (zero padded).  64 x 64 output tile per workgroup,
-// 4 x 4 per thread (rows ty + 16 i, columns tx + 16 j, so that global
-// accesses are coalesced), K in steps of 16 through LDS.
+// Y[r][c] = scale * sum_k A[r][k] X[k][c], r < n, c < ncol: a transform along
+// one axis of a vector stored with that axis slower than the row of length
+// ncol (time: ncol = spatial nodes * nc; transverse axis a: ncol = nodes of
+// the faster axes * nc, one matrix per index of the slower axes).  A is
+// zero padded to a multiple of 64 rows and 16 columns (row length pk).
+// 64 x 64 output tile per workgroup, 4 x 4 per thread (rows ty + 16 i,
+// columns tx + 16 j, so that global accesses are coalesced), K in steps of
+// 16 through LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void tgemm(const cx<T> *__restrict__ A, int pk,
-                                             const cx<T> *__restrict__ X, cx<T> *__restrict__ Y,
-                                             int nt, int64_t ncol, T scale) {
+__device__ __forceinline__ void tgemm_tile(const cx<T> *__restrict__ A, int pk, const cx<T> *__restrict__ X,
+                                  cx<T> *__restrict__ Y, int n, int64_t ncol, int row0, int64_t col0,
+                                  T scale) {
   using C = cx<T>;
   __shared__ C As[16][64];
   __shared__ C Bs[16][64];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t col0 = (int64_t)blockIdx.x * 64;
-  const int row0 = blockIdx.y * 64;
   C acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
     for (int j = 0; j < 4; j++) acc[i][j] = mk<C>(0, 0);
-  for (int k0 = 0; k0 < nt; k0 += 16) {
+  for (int k0 = 0; k0 < n; k0 += 16) {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       const int e = threadIdx.x + 256 * q;
@@ -107,7 +127,7 @@ __global__ __launch_bounds__(256) void tgemm(const cx<T> *__restrict__ A, int pk
       const int kk = e >> 6, c = e & 63;
       const int k = k0 + kk;
       const int64_t col = col0 + c;
-      Bs[kk][c] = (k < nt && col < ncol) ? X[(int64_t)k * ncol + col] : mk<C>(0, 0);
+      Bs[kk][c] = (k < n && col < ncol) ? X[(int64_t)k * ncol + col] : mk<C>(0, 0);
     }
     __syncthreads();
 #pragma unroll
@@ -127,13 +147,22 @@ __global__ __launch_bounds__(256) void tgemm(const cx<T> *__restrict__ A, int pk
 #pragma unroll
   for (int i = 0; i < 4; i++) {
     const int r = row0 + ty + 16 * i;
-    if (r >= nt) continue;
+    if (r >= n) continue;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int64_t c = col0 + tx + 16 * j;
       if (c < ncol) Y[(int64_t)r * ncol + c] = mk<C>(acc[i][j].x * scale, acc[i][j].y * scale);
     }
   }
+}
+
+// grid: (column tiles, row tiles, batches); batch b works on X + b n ncol
+template <typename T>
+__global__ __launch_bounds__(256) void tgemm(const cx<T> *__restrict__ A, int pk,
+                                             const cx<T> *__restrict__ X, cx<T> *__restrict__ Y,
+                                             int n, int64_t ncol, T scale) {
+  const int64_t boff = (int64_t)blockIdx.z * n * ncol;
+  tgemm_tile<T>(A, pk, X + boff, Y + boff, n, ncol, blockIdx.y * 64, (int64_t)blockIdx.x * 64, scale);
 }
 
 template <int NC>
@@ -155,14 +184,12 @@ __device__ inline bool blk_finite(const double2 *a) {
 // corner coupling to node 0), 2 S^{-1}).  One thread per line; the
 // forward sweep writes F_i into the H slot, the backward sweep replaces it.
 template <typename T, int NC, int DS>
-__global__ __launch_bounds__(64) void line_setup(SpecGeom G, const double2 *__restrict__ tw,
-                                                 const double2 *__restrict__ lam,
-                                                 const double *__restrict__ pot,
-                                                 cx<T> *__restrict__ fac, cx<T> *__restrict__ lined,
-                                                 int64_t lines, int *__restrict__ flag) {
+__device__ __forceinline__ void line_setup_one(const SpecGeom &G, const double2 *__restrict__ tw,
+                                               const double2 *__restrict__ lam,
+                                               const double *__restrict__ pot, cx<T> *__restrict__ fac,
+                                               cx<T> *__restrict__ lined, int64_t lines,
+                                               int *__restrict__ flag, int64_t l) {
   constexpr int B = NC * NC;
-  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (l >= lines) return;
   const int n1 = G.n[1];
   const int64_t nperp = G.S / n1;
   const int tq = (int)(l / nperp);
@@ -292,78 +319,149 @@ __global__ __launch_bounds__(64) void line_setup(SpecGeom G, const double2 *__re
   if (!ok) atomicAdd(flag, 1);
 }
 
-template <typename T, int NC>
-__device__ inline void blk_mv(const cx<T> *__restrict__ fac, int64_t base, int64_t lines,
-                              const cx<T> *v, cx<T> *out, bool accum, bool neg) {
-#pragma unroll
-  for (int i = 0; i < NC; i++) {
-    cx<T> s = accum ? out[i] : mk<cx<T>>(0, 0);
-#pragma unroll
-    for (int j = 0; j < NC; j++) {
-      const cx<T> a = fac[base + (int64_t)(i * NC + j) * lines];
-      s = neg ? cfms(s, a, v[j]) : cfma(s, a, v[j]);
-    }
-    out[i] = s;
-  }
+template <typename T, int NC, int DS>
+__global__ __launch_bounds__(64) void line_setup(SpecGeom G, const double2 *__restrict__ tw,
+                                                 const double2 *__restrict__ lam,
+                                                 const double *__restrict__ pot,
+                                                 cx<T> *__restrict__ fac, cx<T> *__restrict__ lined,
+                                                 int64_t lines, int *__restrict__ flag) {
+  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (l < lines) line_setup_one<T, NC, DS>(G, tw, lam, pot, fac, lined, lines, flag, l);
 }
 
 // In-place periodic block-tridiagonal solve along x, one thread per line
 // (line l holds nodes l * n1 .. l * n1 + n1 - 1, nc components each).
 template <typename T, int NC>
-__global__ __launch_bounds__(64) void line_solve(const cx<T> *__restrict__ fac,
-                                                 const cx<T> *__restrict__ lined,
-                                                 cx<T> *__restrict__ X, int n1, int64_t lines) {
+__device__ __forceinline__ void blk_load(const cx<T> *__restrict__ fac, int64_t base, int64_t lines,
+                                         cx<T> (&m)[NC * NC]) {
+#pragma unroll
+  for (int q = 0; q < NC * NC; q++) m[q] = fac[base + (int64_t)q * lines];
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void blk_apply(const cx<T> (&m)[NC * NC], const cx<T> *v, cx<T> *out, bool accum,
+                                          bool neg) {
+#pragma unroll
+  for (int i = 0; i < NC; i++) {
+    cx<T> s = accum ? out[i] : mk<cx<T>>(0, 0);
+#pragma unroll
+    for (int j = 0; j < NC; j++) s = neg ? cfms(s, m[i * NC + j], v[j]) : cfma(s, m[i * NC + j], v[j]);
+    out[i] = s;
+  }
+}
+
+// In-place periodic block-tridiagonal solve along x for line l (nodes
+// l * n1 .. l * n1 + n1 - 1, nc components each).  Each sweep loads the next
+// node's factors and values one step ahead, so the loads overlap the
+// dependent arithmetic of the current node.
+template <typename T, int NC>
+__device__ __forceinline__ void line_solve_one(const cx<T> *__restrict__ fac, const cx<T> *__restrict__ lined,
+                                               cx<T> *__restrict__ X, int n1, int64_t lines, int64_t l) {
   constexpr int B = NC * NC;
-  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (l >= lines) return;
-  cx<T> *x = X + l * n1 * NC;
+  using C = cx<T>;
+  C *x = X + l * n1 * NC;
   auto fb = [&](int i, int slot) { return ((int64_t)i * 4 * B + slot * B) * lines + l; };
-  cx<T> y[NC], v[NC], t[NC];
+  C y[NC], t[NC], v[NC], vn[NC];
+  C Gm[B], Km[B], Gn[B], Kn[B];
 #pragma unroll
-  for (int c = 0; c < NC; c++) y[c] = mk<cx<T>>(0, 0);
+  for (int c = 0; c < NC; c++) y[c] = vn[c] = mk<C>(0, 0);
+#pragma unroll
+  for (int q = 0; q < B; q++) Gn[q] = Kn[q] = mk<C>(0, 0);
   // forward: y_i = G_i v_i - K_i y_{i-1}
-  for (int i = 0; i < n1 - 1; i++) {
+  blk_load<T, NC>(fac, fb(0, 0), lines, Gm);
+  blk_load<T, NC>(fac, fb(0, 1), lines, Km);
 #pragma unroll
-    for (int c = 0; c < NC; c++) v[c] = x[i * NC + c];
-    blk_mv<T, NC>(fac, fb(i, 0), lines, v, t, false, false);
-    blk_mv<T, NC>(fac, fb(i, 1), lines, y, t, true, true);
+  for (int c = 0; c < NC; c++) v[c] = x[c];
+  for (int i = 0; i < n1 - 1; i++) {
+    if (i + 1 < n1 - 1) {
+      blk_load<T, NC>(fac, fb(i + 1, 0), lines, Gn);
+      blk_load<T, NC>(fac, fb(i + 1, 1), lines, Kn);
+#pragma unroll
+      for (int c = 0; c < NC; c++) vn[c] = x[(i + 1) * NC + c];
+    }
+    blk_apply<T, NC>(Gm, v, t, false, false);
+    blk_apply<T, NC>(Km, y, t, true, true);
 #pragma unroll
     for (int c = 0; c < NC; c++) {
       y[c] = t[c];
       x[i * NC + c] = t[c];
     }
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      Gm[q] = Gn[q];
+      Km[q] = Kn[q];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = vn[c];
   }
   // backward: a_i = y_i - E_i a_{i+1}
-  cx<T> alast[NC];
+  C alast[NC];
 #pragma unroll
   for (int c = 0; c < NC; c++) alast[c] = y[c];
-  for (int i = n1 - 3; i >= 0; i--) {
+  if (n1 >= 3) {
+    blk_load<T, NC>(fac, fb(n1 - 3, 2), lines, Gm);
 #pragma unroll
-    for (int c = 0; c < NC; c++) t[c] = x[i * NC + c];
-    blk_mv<T, NC>(fac, fb(i, 2), lines, y, t, true, true);
+    for (int c = 0; c < NC; c++) v[c] = x[(n1 - 3) * NC + c];
+  }
+  for (int i = n1 - 3; i >= 0; i--) {
+    if (i > 0) {
+      blk_load<T, NC>(fac, fb(i - 1, 2), lines, Gn);
+#pragma unroll
+      for (int c = 0; c < NC; c++) vn[c] = x[(i - 1) * NC + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) t[c] = v[c];
+    blk_apply<T, NC>(Gm, y, t, true, true);
 #pragma unroll
     for (int c = 0; c < NC; c++) {
       y[c] = t[c];
       x[i * NC + c] = t[c];
     }
+#pragma unroll
+    for (int q = 0; q < B; q++) Gm[q] = Gn[q];
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = vn[c];
   }
   // last node: S^{-1} (v_{n-1} - L_{n-1} a_{n-2} - U_{n-1} a_0)
 #pragma unroll
   for (int c = 0; c < NC; c++) t[c] = x[(n1 - 1) * NC + c];
-  blk_mv<T, NC>(lined, 0 * B * lines + l, lines, alast, t, true, true);
-  blk_mv<T, NC>(lined, 1 * B * lines + l, lines, y, t, true, true);
-  cx<T> xl[NC];
-  blk_mv<T, NC>(lined, 2 * B * lines + l, lines, t, xl, false, false);
+  blk_load<T, NC>(lined, 0 * B * lines + l, lines, Gm);
+  blk_apply<T, NC>(Gm, alast, t, true, true);
+  blk_load<T, NC>(lined, 1 * B * lines + l, lines, Gm);
+  blk_apply<T, NC>(Gm, y, t, true, true);
+  C xl[NC];
+  blk_load<T, NC>(lined, 2 * B * lines + l, lines, Gm);
+  blk_apply<T, NC>(Gm, t, xl, false, false);
 #pragma unroll
   for (int c = 0; c < NC; c++) x[(n1 - 1) * NC + c] = xl[c];
   // x_i = a_i + H_i x_{n-1}
-  for (int i = 0; i < n1 - 1; i++) {
+  blk_load<T, NC>(fac, fb(0, 3), lines, Gm);
 #pragma unroll
-    for (int c = 0; c < NC; c++) t[c] = x[i * NC + c];
-    blk_mv<T, NC>(fac, fb(i, 3), lines, xl, t, true, false);
+  for (int c = 0; c < NC; c++) v[c] = x[c];
+  for (int i = 0; i < n1 - 1; i++) {
+    if (i + 1 < n1 - 1) {
+      blk_load<T, NC>(fac, fb(i + 1, 3), lines, Gn);
+#pragma unroll
+      for (int c = 0; c < NC; c++) vn[c] = x[(i + 1) * NC + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) t[c] = v[c];
+    blk_apply<T, NC>(Gm, xl, t, true, false);
 #pragma unroll
     for (int c = 0; c < NC; c++) x[i * NC + c] = t[c];
+#pragma unroll
+    for (int q = 0; q < B; q++) Gm[q] = Gn[q];
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = vn[c];
   }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(64) void line_solve(const cx<T> *__restrict__ fac,
+                                                 const cx<T> *__restrict__ lined,
+                                                 cx<T> *__restrict__ X, int n1, int64_t lines) {
+  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (l < lines) line_solve_one<T, NC>(fac, lined, X, n1, lines, l);
 }
 
 static __global__ void zero_i32_flag(int *f) {

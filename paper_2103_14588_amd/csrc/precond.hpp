@@ -9,6 +9,8 @@
 #pragma once
 
 #include <cmath>
+#include <utility>
+#include <vector>
 
 #include "common.hpp"
 #include "krylov.hpp"
@@ -110,69 +112,141 @@ static double host_potential(const dirac_st_problem *p, double x) {
   return 0.0;
 }
 
+// Host-side data of one line preconditioner set-up; kept alive until the
+// stream has consumed the asynchronous copies made from it.
+struct LineStaging {
+  std::vector<double2> tw64, l64, q64, w64;
+  std::vector<float2> tw32, q32, w32;
+  std::vector<double> pot;
+  std::vector<std::vector<double2>> f64s, fi64s;
+  std::vector<std::vector<float2>> f32s, fi32s;
+};
+
+// Geometry, time eigen-decomposition, 1D potential matrix, DFT matrices:
+// computed on the host and copied (asynchronously) into the workspace; the
+// failure flag is cleared.  The factorisation itself is line_factor.
 template <typename T>
-static int line_setup_host(Precond &P, const dirac_st_bsr *A, unsigned char *base, hipStream_t s) {
+static int line_prepare(Precond &P, const dirac_st_bsr *A, unsigned char *base, LineStaging &st,
+                        hipStream_t s) {
   const dirac_st_problem *p = &A->prob;
   DST_CHECK(p->n[0] <= kTimeEigenMax, "line preconditioner needs n_t <= %d", kTimeEigenMax);
   P.line = base;
   P.LL = line_layout(p, P.prec);
   const LineLayout &L = P.LL;
   spec_geom(p, 0.0, P.G);
-  SpecLayout tl{};
-  tl.tw64 = L.tw64;
-  tl.tw32 = L.tw32;
-  if (int rc = spec_twiddles(P.G, base, tl, s)) return rc;
+  int64_t twn = 0;
+  for (int a = 1; a <= p->d; a++) twn += p->n[a];
+  st.tw64.assign(twn, mk<double2>(0, 0));
+  st.tw32.assign(twn, mk<float2>(0, 0));
+  for (int a = 1; a <= p->d; a++)
+    for (int q = 0; q < p->n[a]; q++) {
+      const double th = 2.0 * M_PI * (double)q / (double)p->n[a];
+      st.tw64[P.G.tw_off[a] + q] = mk<double2>(cos(th), -sin(th));
+      st.tw32[P.G.tw_off[a] + q] = mk<float2>((float)cos(th), (float)-sin(th));
+    }
   const int nt = p->n[0], n1 = p->n[1];
   std::vector<std::complex<double>> lam, W, Q;
   if (int rc = time_eigen(nt, p->len[0] / nt, lam, W, Q)) return rc;
-  std::vector<double2> q64((size_t)L.pm * L.pk, mk<double2>(0, 0)), w64(q64.size(), mk<double2>(0, 0)),
-      l64(nt);
-  std::vector<float2> q32(q64.size(), mk<float2>(0, 0)), w32(q64.size(), mk<float2>(0, 0));
+  st.q64.assign((size_t)L.pm * L.pk, mk<double2>(0, 0));
+  st.w64.assign(st.q64.size(), mk<double2>(0, 0));
+  st.q32.assign(st.q64.size(), mk<float2>(0, 0));
+  st.w32.assign(st.q64.size(), mk<float2>(0, 0));
+  st.l64.resize(nt);
   for (int r = 0; r < nt; r++) {
-    l64[r] = mk<double2>(lam[r].real(), lam[r].imag());
+    st.l64[r] = mk<double2>(lam[r].real(), lam[r].imag());
     for (int c = 0; c < nt; c++) {
       const size_t e = (size_t)r * L.pk + c;
       const std::complex<double> qv = Q[(size_t)r * nt + c], wv = W[(size_t)r * nt + c];
-      q64[e] = mk<double2>(qv.real(), qv.imag());
-      w64[e] = mk<double2>(wv.real(), wv.imag());
-      q32[e] = mk<float2>((float)qv.real(), (float)qv.imag());
-      w32[e] = mk<float2>((float)wv.real(), (float)wv.imag());
+      st.q64[e] = mk<double2>(qv.real(), qv.imag());
+      st.w64[e] = mk<double2>(wv.real(), wv.imag());
+      st.q32[e] = mk<float2>((float)qv.real(), (float)qv.imag());
+      st.w32[e] = mk<float2>((float)wv.real(), (float)wv.imag());
     }
   }
   // P_x: diagonal and (i, i+1) entries, 2-point Gauss on every element
-  std::vector<double> pot(2 * (size_t)n1, 0.0);
+  st.pot.assign(2 * (size_t)n1, 0.0);
   const double h1 = p->len[1] / n1, r3 = 0.57735026918962576451;
   for (int e = 0; e < n1; e++)
     for (int q = 0; q < 2; q++) {
       const double xi = 0.5 * (1.0 + (q ? r3 : -r3));
       const double w = 0.5 * h1 * host_potential(p, (e + xi) * h1);
-      pot[e] += w * (1.0 - xi) * (1.0 - xi);
-      pot[(e + 1) % n1] += w * xi * xi;
-      pot[n1 + e] += w * (1.0 - xi) * xi;
+      st.pot[e] += w * (1.0 - xi) * (1.0 - xi);
+      st.pot[(e + 1) % n1] += w * xi * xi;
+      st.pot[n1 + e] += w * (1.0 - xi) * xi;
     }
-  DST_HIP(hipMemcpyAsync(base + L.lam, l64.data(), l64.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-  DST_HIP(hipMemcpyAsync(base + L.q64, q64.data(), q64.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-  DST_HIP(hipMemcpyAsync(base + L.w64, w64.data(), w64.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-  DST_HIP(hipMemcpyAsync(base + L.q32, q32.data(), q32.size() * sizeof(float2), hipMemcpyHostToDevice, s));
-  DST_HIP(hipMemcpyAsync(base + L.w32, w32.data(), w32.size() * sizeof(float2), hipMemcpyHostToDevice, s));
-  DST_HIP(hipMemcpyAsync(base + L.pot, pot.data(), pot.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  int *flag = (int *)(base + L.flag);
-  zero_i32_flag<<<1, 64, 0, s>>>(flag);
+  auto up = [&](size_t off, const void *src, size_t bytes) -> int {
+    DST_HIP(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s));
+    return 0;
+  };
+  int rc = 0;
+  rc = rc ? rc : up(L.tw64, st.tw64.data(), twn * sizeof(double2));
+  rc = rc ? rc : up(L.tw32, st.tw32.data(), twn * sizeof(float2));
+  rc = rc ? rc : up(L.lam, st.l64.data(), st.l64.size() * sizeof(double2));
+  rc = rc ? rc : up(L.q64, st.q64.data(), st.q64.size() * sizeof(double2));
+  rc = rc ? rc : up(L.w64, st.w64.data(), st.w64.size() * sizeof(double2));
+  rc = rc ? rc : up(L.q32, st.q32.data(), st.q32.size() * sizeof(float2));
+  rc = rc ? rc : up(L.w32, st.w32.data(), st.w32.size() * sizeof(float2));
+  rc = rc ? rc : up(L.pot, st.pot.data(), st.pot.size() * sizeof(double));
+  if (rc) return rc;
+  // DFT matrices of the transverse axes: F[k][j] = exp(-2 pi i k j / n),
+  // F^{-1}[j][k] = exp(2 pi i j k / n) / n
+  for (int a = 2; a <= p->d; a++) {
+    const int n = p->n[a], pk = L.dpk[a];
+    const size_t e = (size_t)L.dpm[a] * pk;
+    st.f64s.emplace_back(e, mk<double2>(0, 0));
+    st.fi64s.emplace_back(e, mk<double2>(0, 0));
+    st.f32s.emplace_back(e, mk<float2>(0, 0));
+    st.fi32s.emplace_back(e, mk<float2>(0, 0));
+    for (int k = 0; k < n; k++)
+      for (int j = 0; j < n; j++) {
+        const double th = 2.0 * M_PI * (double)((int64_t)k * j % n) / n;
+        const double c = cos(th), sn = sin(th);
+        st.f64s.back()[(size_t)k * pk + j] = mk<double2>(c, -sn);
+        st.fi64s.back()[(size_t)k * pk + j] = mk<double2>(c / n, sn / n);
+        st.f32s.back()[(size_t)k * pk + j] = mk<float2>((float)c, (float)-sn);
+        st.fi32s.back()[(size_t)k * pk + j] = mk<float2>((float)(c / n), (float)(sn / n));
+      }
+    if ((rc = up(L.f64[a], st.f64s.back().data(), e * 16))) return rc;
+    if ((rc = up(L.fi64[a], st.fi64s.back().data(), e * 16))) return rc;
+    if ((rc = up(L.f32[a], st.f32s.back().data(), e * 8))) return rc;
+    if ((rc = up(L.fi32[a], st.fi32s.back().data(), e * 8))) return rc;
+  }
+  zero_i32_flag<<<1, 64, 0, s>>>((int *)(base + L.flag));
+  DST_LAUNCHED();
+  return 0;
+}
+
+// Per-line factorisation of one operator (after line_prepare).
+template <typename T>
+static int line_factor(const Precond &P, hipStream_t s) {
+  const LineLayout &L = P.LL;
+  unsigned char *base = P.line;
   const unsigned g = (unsigned)((L.lines + 63) / 64);
   const double2 *tw64 = (const double2 *)(base + L.tw64);
   const double2 *lamd = (const double2 *)(base + L.lam);
   const double *potd = (const double *)(base + L.pot);
   cx<T> *fac = (cx<T> *)(base + L.fac), *lined = (cx<T> *)(base + L.lined);
-  if (p->d == 1)
+  int *flag = (int *)(base + L.flag);
+  if (P.G.d == 1)
     line_setup<T, 2, 1><<<g, 64, 0, s>>>(P.G, tw64, lamd, potd, fac, lined, L.lines, flag);
-  else if (p->d == 2)
+  else if (P.G.d == 2)
     line_setup<T, 2, 2><<<g, 64, 0, s>>>(P.G, tw64, lamd, potd, fac, lined, L.lines, flag);
   else
     line_setup<T, 4, 3><<<g, 64, 0, s>>>(P.G, tw64, lamd, potd, fac, lined, L.lines, flag);
   DST_LAUNCHED();
+  return 0;
+}
+
+// Line preconditioner set-up of one operator: prepare, factorise, check the
+// failure flag (synchronises the stream).
+template <typename T>
+static int line_setup_host(Precond &P, const dirac_st_bsr *A, unsigned char *base, hipStream_t s) {
+  LineStaging st;
+  if (int rc = line_prepare<T>(P, A, base, st, s)) return rc;
+  if (int rc = line_factor<T>(P, s)) return rc;
   int bad = 0;
-  DST_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  // the host staging vectors above live on this frame: wait for every copy
+  DST_HIP(hipMemcpyAsync(&bad, base + P.LL.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  // the staging vectors live on this frame: wait for every copy
   DST_HIP(hipStreamSynchronize(s));
   DST_CHECK(bad == 0, "line preconditioner: %d singular or non-finite line factorisations", bad);
   return 0;
@@ -282,37 +356,45 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
     const SpecGeom &G = P.G;
     const LineLayout &L = P.LL;
     const bool dbl = sizeof(T) == 8;
-    const cx<T> *tw = (const cx<T> *)(P.line + (dbl ? L.tw64 : L.tw32));
     const cx<T> *Qm = (const cx<T> *)(P.line + (dbl ? L.q64 : L.q32));
     const cx<T> *Wm = (const cx<T> *)(P.line + (dbl ? L.w64 : L.w32));
-    cx<T> *buf = (cx<T> *)(P.line + L.buf);
+    cx<T> *b1 = (cx<T> *)(P.line + L.buf), *b2 = (cx<T> *)(P.line + L.buf2);
     const int64_t ncol = G.S * G.nc;
-    const dim3 gg((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64));
-    // buf = Q v along time
-    tgemm<T><<<gg, 256, 0, s>>>(Qm, L.pk, v, buf, G.nt, ncol, (T)1);
+    // b1 = Q v along time
+    tgemm<T><<<dim3((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64), 1), 256, 0, s>>>(
+        Qm, L.pk, v, b1, G.nt, ncol, (T)1);
     DST_LAUNCHED();
-    // DFT over the transverse axes (in place)
-    int64_t stride = (int64_t)G.nc * G.n[1];
-    for (int a = 2; a <= G.d; a++) {
-      if (int rc = axis_transform<T>(G, tw, buf, buf, a, stride, -1, (T)1, s)) return rc;
-      stride *= G.n[a];
+    // transverse DFTs, slowest axis first, ping-pong b1 <-> b2
+    auto transverse = [&](int a, bool inverse, const cx<T> *in, cx<T> *out) -> int {
+      int64_t cols = G.nc, batches = G.nt;
+      for (int q = 1; q < a; q++) cols *= G.n[q];
+      for (int q = a + 1; q <= G.d; q++) batches *= G.n[q];
+      const cx<T> *F = (const cx<T> *)(P.line + (inverse ? (dbl ? L.fi64[a] : L.fi32[a])
+                                                          : (dbl ? L.f64[a] : L.f32[a])));
+      tgemm<T><<<dim3((unsigned)((cols + 63) / 64), (unsigned)(L.dpm[a] / 64), (unsigned)batches), 256, 0,
+                 s>>>(F, L.dpk[a], in, out, G.n[a], cols, (T)1);
+      DST_LAUNCHED();
+      return 0;
+    };
+    cx<T> *cur = b1, *oth = b2;
+    for (int a = G.d; a >= 2; a--) {
+      if (int rc = transverse(a, false, cur, oth)) return rc;
+      std::swap(cur, oth);
     }
     const unsigned gl = (unsigned)((L.lines + 63) / 64);
     const cx<T> *fac = (const cx<T> *)(P.line + L.fac), *lined = (const cx<T> *)(P.line + L.lined);
     if (G.nc == 2)
-      line_solve<T, 2><<<gl, 64, 0, s>>>(fac, lined, buf, G.n[1], L.lines);
+      line_solve<T, 2><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
     else
-      line_solve<T, 4><<<gl, 64, 0, s>>>(fac, lined, buf, G.n[1], L.lines);
+      line_solve<T, 4><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
     DST_LAUNCHED();
-    stride = (int64_t)G.nc * G.n[1];
-    const int64_t nperp = G.S / G.n[1];
     for (int a = 2; a <= G.d; a++) {
-      const T sc = a == G.d ? (T)(1.0 / (double)nperp) : (T)1;
-      if (int rc = axis_transform<T>(G, tw, buf, buf, a, stride, 1, sc, s)) return rc;
-      stride *= G.n[a];
+      if (int rc = transverse(a, true, cur, oth)) return rc;
+      std::swap(cur, oth);
     }
-    // z = scale * W buf along time
-    tgemm<T><<<gg, 256, 0, s>>>(Wm, L.pk, buf, z, G.nt, ncol, (T)scale);
+    // z = scale * W cur along time
+    tgemm<T><<<dim3((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64), 1), 256, 0, s>>>(
+        Wm, L.pk, cur, z, G.nt, ncol, (T)scale);
     DST_LAUNCHED();
     return 0;
   }

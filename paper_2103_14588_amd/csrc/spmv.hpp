@@ -40,7 +40,7 @@ __device__ inline float2 chunk_mac<float>(float2 acc, fv4 v, fv4 x) {
 
 // Rows [tile * 256/G, (tile + 1) * 256/G) of one operator, one workgroup.
 template <typename T, int NC, int G, bool RESID>
-__device__ inline void spmv_tile(int64_t tile, int64_t nrows, const int32_t *__restrict__ rp,
+__device__ __forceinline__ void spmv_tile(int64_t tile, int64_t nrows, const int32_t *__restrict__ rp,
                                  const int32_t *__restrict__ ci, const cx<T> *__restrict__ val,
                                  const cx<T> *__restrict__ x, const cx<T> *__restrict__ bvec,
                                  cx<T> *__restrict__ y, T alpha) {

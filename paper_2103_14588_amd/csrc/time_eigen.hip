@@ -205,7 +205,9 @@ struct EigenEntry {
 };
 std::mutex g_eig_mu;
 std::map<std::pair<int, double>, EigenEntry> g_eig;
-constexpr size_t kEigenCacheEntries = 16;
+size_t g_eig_bytes = 0;
+constexpr size_t kEigenCacheBytes = size_t(256) << 20;
+size_t entry_bytes(int n) { return (2 * (size_t)n * n + n) * sizeof(cd); }
 }  // namespace
 
 int time_eigen(int n, double h, std::vector<cd> &lam, std::vector<cd> &W, std::vector<cd> &Q) {
@@ -222,8 +224,13 @@ int time_eigen(int n, double h, std::vector<cd> &lam, std::vector<cd> &W, std::v
   }
   if (int rc = time_eigen_core(n, h, lam, W, Q)) return rc;
   std::lock_guard<std::mutex> lk(g_eig_mu);
-  if (g_eig.size() >= kEigenCacheEntries) g_eig.erase(g_eig.begin());
+  if (g_eig.count(key) || entry_bytes(n) > kEigenCacheBytes) return 0;
+  while (!g_eig.empty() && g_eig_bytes + entry_bytes(n) > kEigenCacheBytes) {
+    g_eig_bytes -= entry_bytes(g_eig.begin()->first.first);
+    g_eig.erase(g_eig.begin());
+  }
   g_eig[key] = EigenEntry{lam, W, Q};
+  g_eig_bytes += entry_bytes(n);
   return 0;
 }
 
