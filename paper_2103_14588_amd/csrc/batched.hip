@@ -279,10 +279,8 @@ template <typename T, int NC>
 __global__ __launch_bounds__(64) void g_line_solve(const LineJob *__restrict__ J, WorkList L, int buf) {
   int64_t tile;
   const LineJob &q = J[find_sys(L, tile)];
-  const int64_t l = tile * 64 + threadIdx.x;
-  if (l < q.lines)
-    line_solve_one<T, NC>((const cx<T> *)q.fac, (const cx<T> *)q.lined, (cx<T> *)(buf == 1 ? q.b1 : q.b2),
-                          q.n[1], q.lines, l);
+  line_solve_wg<T, NC, kLineChunk>((const cx<T> *)q.fac, (const cx<T> *)q.lined,
+                                   (cx<T> *)(buf == 1 ? q.b1 : q.b2), q.n[1], q.lines, tile * 64);
 }
 
 // x += sum_{i < k} Z_i coef_i (FP64 accumulation)

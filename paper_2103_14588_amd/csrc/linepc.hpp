@@ -350,118 +350,146 @@ __device__ __forceinline__ void blk_apply(const cx<T> (&m)[NC * NC], const cx<T>
   }
 }
 
-// In-place periodic block-tridiagonal solve along x for line l (nodes
-// l * n1 .. l * n1 + n1 - 1, nc components each).  Each sweep loads the next
-// node's factors and values one step ahead, so the loads overlap the
-// dependent arithmetic of the current node.
-template <typename T, int NC>
-__device__ __forceinline__ void line_solve_one(const cx<T> *__restrict__ fac, const cx<T> *__restrict__ lined,
-                                               cx<T> *__restrict__ X, int n1, int64_t lines, int64_t l) {
-  constexpr int B = NC * NC;
+// In-place periodic block-tridiagonal solve along x for the 64 lines
+// l0 .. l0 + 63 of one workgroup (line l holds nodes l * n1 .. l * n1 + n1 - 1,
+// nc components each); thread t owns line l0 + t.  The line values move
+// through LDS in chunks of CH nodes: the workgroup loads a chunk of all its
+// lines cooperatively (contiguous 16-byte pieces, coalesced), each thread
+// sweeps its own line inside the chunk, and the chunk is stored back the same
+// way.  The factors are laid out [node][entry][line], so their per-thread
+// loads are coalesced already; they are fetched one node ahead.
+template <typename T, int NC, int CH>
+__device__ __forceinline__ void line_solve_wg(const cx<T> *__restrict__ fac, const cx<T> *__restrict__ lined,
+                                              cx<T> *__restrict__ X, int n1, int64_t lines, int64_t l0) {
+  constexpr int B = NC * NC, CL = CH * NC, RL = CL + 1;  // padded LDS row
   using C = cx<T>;
-  C *x = X + l * n1 * NC;
-  auto fb = [&](int i, int slot) { return ((int64_t)i * 4 * B + slot * B) * lines + l; };
-  C y[NC], t[NC], v[NC], vn[NC];
-  C Gm[B], Km[B], Gn[B], Kn[B];
+  __shared__ C sh[64][RL];
+  const int t = threadIdx.x;
+  const int64_t l = l0 + t;
+  const bool own = l < lines;
+  const int64_t lc = own ? l : l0;  // a valid line for the factor addresses of idle threads
+  auto fb = [&](int i, int slot) { return ((int64_t)i * 4 * B + slot * B) * lines + lc; };
+  auto load_chunk = [&](int i0) {
+#pragma unroll 4
+    for (int k = 0; k < CL; k++) {
+      const int e = t + 64 * k, ln = e / CL, r = e - ln * CL;
+      const bool ok = l0 + ln < lines && i0 + r / NC < n1;
+      sh[ln][r] = ok ? X[(l0 + ln) * n1 * NC + (int64_t)i0 * NC + r] : mk<C>(0, 0);
+    }
+    __syncthreads();
+  };
+  auto store_chunk = [&](int i0) {
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < CL; k++) {
+      const int e = t + 64 * k, ln = e / CL, r = e - ln * CL;
+      if (l0 + ln < lines && i0 + r / NC < n1) X[(l0 + ln) * n1 * NC + (int64_t)i0 * NC + r] = sh[ln][r];
+    }
+    __syncthreads();
+  };
+  C y[NC], tv[NC], Gm[B], Km[B], Gn[B], Kn[B];
 #pragma unroll
-  for (int c = 0; c < NC; c++) y[c] = vn[c] = mk<C>(0, 0);
+  for (int c = 0; c < NC; c++) y[c] = mk<C>(0, 0);
 #pragma unroll
   for (int q = 0; q < B; q++) Gn[q] = Kn[q] = mk<C>(0, 0);
-  // forward: y_i = G_i v_i - K_i y_{i-1}
+  // forward: y_i = G_i v_i - K_i y_{i-1}, nodes 0 .. n1-2
   blk_load<T, NC>(fac, fb(0, 0), lines, Gm);
   blk_load<T, NC>(fac, fb(0, 1), lines, Km);
+  for (int i0 = 0; i0 < n1 - 1; i0 += CH) {
+    load_chunk(i0);
+    const int ie = min(i0 + CH, n1 - 1);
+    for (int i = i0; i < ie; i++) {
+      if (i + 1 < n1 - 1) {
+        blk_load<T, NC>(fac, fb(i + 1, 0), lines, Gn);
+        blk_load<T, NC>(fac, fb(i + 1, 1), lines, Kn);
+      }
+      C v[NC];
 #pragma unroll
-  for (int c = 0; c < NC; c++) v[c] = x[c];
-  for (int i = 0; i < n1 - 1; i++) {
-    if (i + 1 < n1 - 1) {
-      blk_load<T, NC>(fac, fb(i + 1, 0), lines, Gn);
-      blk_load<T, NC>(fac, fb(i + 1, 1), lines, Kn);
+      for (int c = 0; c < NC; c++) v[c] = sh[t][(i - i0) * NC + c];
+      blk_apply<T, NC>(Gm, v, tv, false, false);
+      blk_apply<T, NC>(Km, y, tv, true, true);
 #pragma unroll
-      for (int c = 0; c < NC; c++) vn[c] = x[(i + 1) * NC + c];
+      for (int c = 0; c < NC; c++) {
+        y[c] = tv[c];
+        sh[t][(i - i0) * NC + c] = tv[c];
+      }
+#pragma unroll
+      for (int q = 0; q < B; q++) {
+        Gm[q] = Gn[q];
+        Km[q] = Kn[q];
+      }
     }
-    blk_apply<T, NC>(Gm, v, t, false, false);
-    blk_apply<T, NC>(Km, y, t, true, true);
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-      y[c] = t[c];
-      x[i * NC + c] = t[c];
-    }
-#pragma unroll
-    for (int q = 0; q < B; q++) {
-      Gm[q] = Gn[q];
-      Km[q] = Kn[q];
-    }
-#pragma unroll
-    for (int c = 0; c < NC; c++) v[c] = vn[c];
+    store_chunk(i0);
   }
-  // backward: a_i = y_i - E_i a_{i+1}
+  // backward: a_i = y_i - E_i a_{i+1}, nodes n1-3 .. 0
   C alast[NC];
 #pragma unroll
   for (int c = 0; c < NC; c++) alast[c] = y[c];
-  if (n1 >= 3) {
-    blk_load<T, NC>(fac, fb(n1 - 3, 2), lines, Gm);
+  blk_load<T, NC>(fac, fb(n1 - 3, 2), lines, Gm);
+  for (int i0 = ((n1 - 3) / CH) * CH; i0 >= 0; i0 -= CH) {
+    load_chunk(i0);
+    for (int i = min(i0 + CH - 1, n1 - 3); i >= i0; i--) {
+      if (i > 0) blk_load<T, NC>(fac, fb(i - 1, 2), lines, Gn);
 #pragma unroll
-    for (int c = 0; c < NC; c++) v[c] = x[(n1 - 3) * NC + c];
-  }
-  for (int i = n1 - 3; i >= 0; i--) {
-    if (i > 0) {
-      blk_load<T, NC>(fac, fb(i - 1, 2), lines, Gn);
+      for (int c = 0; c < NC; c++) tv[c] = sh[t][(i - i0) * NC + c];
+      blk_apply<T, NC>(Gm, y, tv, true, true);
 #pragma unroll
-      for (int c = 0; c < NC; c++) vn[c] = x[(i - 1) * NC + c];
+      for (int c = 0; c < NC; c++) {
+        y[c] = tv[c];
+        sh[t][(i - i0) * NC + c] = tv[c];
+      }
+#pragma unroll
+      for (int q = 0; q < B; q++) Gm[q] = Gn[q];
     }
-#pragma unroll
-    for (int c = 0; c < NC; c++) t[c] = v[c];
-    blk_apply<T, NC>(Gm, y, t, true, true);
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-      y[c] = t[c];
-      x[i * NC + c] = t[c];
-    }
-#pragma unroll
-    for (int q = 0; q < B; q++) Gm[q] = Gn[q];
-#pragma unroll
-    for (int c = 0; c < NC; c++) v[c] = vn[c];
+    store_chunk(i0);
   }
   // last node: S^{-1} (v_{n-1} - L_{n-1} a_{n-2} - U_{n-1} a_0)
-#pragma unroll
-  for (int c = 0; c < NC; c++) t[c] = x[(n1 - 1) * NC + c];
-  blk_load<T, NC>(lined, 0 * B * lines + l, lines, Gm);
-  blk_apply<T, NC>(Gm, alast, t, true, true);
-  blk_load<T, NC>(lined, 1 * B * lines + l, lines, Gm);
-  blk_apply<T, NC>(Gm, y, t, true, true);
   C xl[NC];
-  blk_load<T, NC>(lined, 2 * B * lines + l, lines, Gm);
-  blk_apply<T, NC>(Gm, t, xl, false, false);
+  {
+    const int64_t ll = lc - l0;  // 0 for idle threads; their results are never stored
+    (void)ll;
 #pragma unroll
-  for (int c = 0; c < NC; c++) x[(n1 - 1) * NC + c] = xl[c];
-  // x_i = a_i + H_i x_{n-1}
+    for (int c = 0; c < NC; c++) tv[c] = X[lc * n1 * NC + (int64_t)(n1 - 1) * NC + c];
+    blk_load<T, NC>(lined, 0 * B * lines + lc, lines, Gm);
+    blk_apply<T, NC>(Gm, alast, tv, true, true);
+    blk_load<T, NC>(lined, 1 * B * lines + lc, lines, Gm);
+    blk_apply<T, NC>(Gm, y, tv, true, true);
+    blk_load<T, NC>(lined, 2 * B * lines + lc, lines, Gm);
+    blk_apply<T, NC>(Gm, tv, xl, false, false);
+  }
+  __syncthreads();  // every thread has read v_{n-1} of its line before any is overwritten
+  if (own) {
+#pragma unroll
+    for (int c = 0; c < NC; c++) X[l * n1 * NC + (int64_t)(n1 - 1) * NC + c] = xl[c];
+  }
+  __syncthreads();
+  // x_i = a_i + H_i x_{n-1}, nodes 0 .. n1-2
   blk_load<T, NC>(fac, fb(0, 3), lines, Gm);
+  for (int i0 = 0; i0 < n1 - 1; i0 += CH) {
+    load_chunk(i0);
+    const int ie = min(i0 + CH, n1 - 1);
+    for (int i = i0; i < ie; i++) {
+      if (i + 1 < n1 - 1) blk_load<T, NC>(fac, fb(i + 1, 3), lines, Gn);
 #pragma unroll
-  for (int c = 0; c < NC; c++) v[c] = x[c];
-  for (int i = 0; i < n1 - 1; i++) {
-    if (i + 1 < n1 - 1) {
-      blk_load<T, NC>(fac, fb(i + 1, 3), lines, Gn);
+      for (int c = 0; c < NC; c++) tv[c] = sh[t][(i - i0) * NC + c];
+      blk_apply<T, NC>(Gm, xl, tv, true, false);
 #pragma unroll
-      for (int c = 0; c < NC; c++) vn[c] = x[(i + 1) * NC + c];
+      for (int c = 0; c < NC; c++) sh[t][(i - i0) * NC + c] = tv[c];
+#pragma unroll
+      for (int q = 0; q < B; q++) Gm[q] = Gn[q];
     }
-#pragma unroll
-    for (int c = 0; c < NC; c++) t[c] = v[c];
-    blk_apply<T, NC>(Gm, xl, t, true, false);
-#pragma unroll
-    for (int c = 0; c < NC; c++) x[i * NC + c] = t[c];
-#pragma unroll
-    for (int q = 0; q < B; q++) Gm[q] = Gn[q];
-#pragma unroll
-    for (int c = 0; c < NC; c++) v[c] = vn[c];
+    store_chunk(i0);
   }
 }
+
+// chunk length of the LDS-staged line solve (nodes)
+constexpr int kLineChunk = 8;
 
 template <typename T, int NC>
 __global__ __launch_bounds__(64) void line_solve(const cx<T> *__restrict__ fac,
                                                  const cx<T> *__restrict__ lined,
                                                  cx<T> *__restrict__ X, int n1, int64_t lines) {
-  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (l < lines) line_solve_one<T, NC>(fac, lined, X, n1, lines, l);
+  line_solve_wg<T, NC, kLineChunk>(fac, lined, X, n1, lines, (int64_t)blockIdx.x * 64);
 }
 
 static __global__ void zero_i32_flag(int *f) {
