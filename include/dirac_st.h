@@ -271,6 +271,26 @@ int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x, const dirac_st
  * decomposition does not pass its own residual and reconstruction checks. */
 int dirac_st_time_eigen(int32_t nt, double ht, double *lam, double *W, double *Q);
 
+/* ------------------------------------------------------------------ timing
+ * Measurement support: HIP events recorded on the launch stream around the
+ * launches of selected kernels, so that a caller can read the average
+ * duration of a kernel while it runs inside the solver. */
+enum {
+  DIRAC_ST_TIMED_SPMV64 = 0,   /* y = A x, complex128 (dirac_st_spmv and inside GMRES) */
+  DIRAC_ST_TIMED_SPMV32 = 1,   /* y = A x, complex64 */
+  DIRAC_ST_TIMED_RESID64 = 2,  /* r = b - A x, complex128 (the FP64 true residual) */
+  DIRAC_ST_TIMED_ASSEMBLE = 3, /* the block-CSR assembly kernel */
+  DIRAC_ST_TIMED_COUNT = 4
+};
+
+/* Host.  on = 1 starts recording (earlier records are dropped), on = 0 stops.
+ * Process-wide; recording adds two event records per timed launch. */
+int dirac_st_timing(int32_t on);
+
+/* Host.  Number of recorded launches of `kind` and their summed duration in
+ * milliseconds (waits for the recorded events). */
+int dirac_st_timing_read(int32_t kind, int64_t *count, double *total_ms);
+
 /* ------------------------------------------------------------------ batches
  * Many independent systems (Alg. 1 run for several initial fields, meshes or
  * potentials) solved together: every phase of an Arnoldi step is one launch
@@ -317,7 +337,7 @@ size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys);
 /* y[i] = A[i] x[i] for every system in one launch (Sec. 2.2 product).  A, x, y:
  * host arrays of nsys pointers; x[i], y[i] device vectors of complex128
  * (prec 64, val64) or complex64 (prec 32, val32).  lanes: lanes per block row,
- * 4, 8 or 16 for nc = 2; 64 (or 32 at prec 32) for nc = 4.  Enqueues only
+ * 4, 8, 16 or 32 for nc = 2; 64 (or 32 at prec 32) for nc = 4.  Enqueues only
  * (the small descriptor copy is synchronous). */
 int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A, int32_t prec, const void *const *x,
                           void *const *y, int32_t lanes, void *work, size_t work_bytes, void *stream);

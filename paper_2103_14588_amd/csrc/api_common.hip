@@ -1,6 +1,8 @@
 // api_common.hip -- error reporting, problem validation and the size query of
 // the C ABI.
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -16,6 +18,52 @@ void set_error(const char *fmt, ...) {
 }
 
 void clear_error() { g_err[0] = 0; }
+
+// ------------------------------------------------------------ kernel timers
+namespace {
+struct TimedLaunch {
+  int kind;
+  hipEvent_t ev[2];
+};
+std::mutex g_kt_mu;
+bool g_kt_on = false;
+std::vector<TimedLaunch> g_kt;   // launches recorded since timing was switched on
+std::vector<hipEvent_t> g_kt_pool;
+
+hipEvent_t kt_event() {
+  if (!g_kt_pool.empty()) {
+    hipEvent_t e = g_kt_pool.back();
+    g_kt_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void kt_clear() {
+  for (TimedLaunch &t : g_kt) {
+    g_kt_pool.push_back(t.ev[0]);
+    g_kt_pool.push_back(t.ev[1]);
+  }
+  g_kt.clear();
+}
+}  // namespace
+
+int kt_start(int kind, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_kt_mu);
+  if (!g_kt_on) return -1;
+  TimedLaunch t{kind, {kt_event(), kt_event()}};
+  if (!t.ev[0] || !t.ev[1] || hipEventRecord(t.ev[0], s) != hipSuccess) return -1;
+  g_kt.push_back(t);
+  return (int)g_kt.size() - 1;
+}
+
+void kt_stop(int token, hipStream_t s) {
+  if (token < 0) return;
+  std::lock_guard<std::mutex> lk(g_kt_mu);
+  if (token < (int)g_kt.size()) (void)hipEventRecord(g_kt[token].ev[1], s);
+}
 
 int validate_problem(const dirac_st_problem *p) {
   DST_CHECK(p != nullptr, "problem is NULL");
@@ -68,5 +116,33 @@ extern "C" int dirac_st_sizes(const dirac_st_problem *prob, int64_t *nrows, int6
   DST_CHECK(nrows && nnzb, "null output pointer");
   *nrows = dst::spatial_nodes(prob) * prob->n[0];
   *nnzb = dst::total_blocks(prob);
+  return DIRAC_ST_OK;
+}
+
+extern "C" int dirac_st_timing(int32_t on) {
+  dst::clear_error();
+  std::lock_guard<std::mutex> lk(dst::g_kt_mu);
+  dst::kt_clear();
+  dst::g_kt_on = on != 0;
+  return DIRAC_ST_OK;
+}
+
+extern "C" int dirac_st_timing_read(int32_t kind, int64_t *count, double *total_ms) {
+  dst::clear_error();
+  DST_CHECK(count && total_ms, "count and total_ms must be set");
+  DST_CHECK(kind >= 0 && kind < DIRAC_ST_TIMED_COUNT, "unknown timed kernel %d", kind);
+  std::lock_guard<std::mutex> lk(dst::g_kt_mu);
+  int64_t n = 0;
+  double ms = 0.0;
+  for (const auto &t : dst::g_kt) {
+    if (t.kind != kind) continue;
+    DST_HIP(hipEventSynchronize(t.ev[1]));
+    float e = 0.f;
+    DST_HIP(hipEventElapsedTime(&e, t.ev[0], t.ev[1]));
+    ms += e;
+    n++;
+  }
+  *count = n;
+  *total_ms = ms;
   return DIRAC_ST_OK;
 }

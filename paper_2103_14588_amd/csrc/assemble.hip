@@ -454,15 +454,19 @@ extern "C" int dirac_st_assemble(const dirac_st_problem *prob, const void *psi0,
   float2 *v32 = (float2 *)A->val32, *bj32 = (float2 *)A->bjinv32;
   const double2 *ps = (const double2 *)psi0;
   double2 *bb = (double2 *)b;
+  const int tk = kt_start(DIRAC_ST_TIMED_ASSEMBLE, st);
   if (P.d == 1) {
     assemble_kernel<2, 1, 256><<<g256, 256, 0, st>>>(P, A->row_ptr, A->col_idx, v64, v32, bj64, bj32, dsing);
+    kt_stop(tk, st);
     if (b) rhs_kernel<2, 1><<<grow, 256, 0, st>>>(P, ps, bb);
   } else if (P.d == 2) {
     assemble_kernel<2, 2, 256><<<g256, 256, 0, st>>>(P, A->row_ptr, A->col_idx, v64, v32, bj64, bj32, dsing);
+    kt_stop(tk, st);
     if (b) rhs_kernel<2, 2><<<grow, 256, 0, st>>>(P, ps, bb);
   } else {
     assemble_kernel<4, 3, 128><<<(unsigned)((P.nnzb + 127) / 128), 128, 0, st>>>(
         P, A->row_ptr, A->col_idx, v64, v32, bj64, bj32, dsing);
+    kt_stop(tk, st);
     if (b) rhs_kernel<4, 3><<<grow, 256, 0, st>>>(P, ps, bb);
   }
   DST_LAUNCHED();

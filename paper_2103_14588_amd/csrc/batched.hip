@@ -441,6 +441,7 @@ static hipError_t launch_g_spmv(int G, const BSys *S, const WorkList &L, unsigne
   if (NC == 2) {
     if (G == 4) g_spmv<T, 2, 4, MODE><<<nwg, 256, 0, s>>>(S, L, j);
     else if (G == 8) g_spmv<T, 2, 8, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+    else if (G == 32) g_spmv<T, 2, 32, MODE><<<nwg, 256, 0, s>>>(S, L, j);
     else g_spmv<T, 2, 16, MODE><<<nwg, 256, 0, s>>>(S, L, j);
   } else {
     if (G == 32 && sizeof(T) == 4) g_spmv<T, 4, 32, MODE><<<nwg, 256, 0, s>>>(S, L, j);
@@ -466,7 +467,7 @@ static hipError_t launch_g_cgs(int mk, const BSys *S, const WorkList &L, unsigne
 
 // lanes per block row the SpMV may use, for (block size, precision)
 static std::vector<int> lane_candidates(int nc, int prec) {
-  if (nc == 2) return std::vector<int>{4, 8, 16};
+  if (nc == 2) return std::vector<int>{4, 8, 16, 32};
   return prec == 32 ? std::vector<int>{32, 64} : std::vector<int>{64};
 }
 
@@ -652,7 +653,7 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
 
   std::vector<int> all(nsys);
   for (int i = 0; i < nsys; i++) all[i] = i;
-  const int Gres = nc == 2 ? 16 : 64;  // FP64 residual SpMV
+  const int Gres = nc == 2 ? 32 : 64;  // FP64 residual SpMV
   int G = 0;
   if (int rc = choose_lanes<T>(hs, dS, lists, all, Gres, G, s)) return rc;
 
@@ -961,7 +962,7 @@ extern "C" int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A,
   DST_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
   std::vector<int> all(nsys);
   for (int i = 0; i < nsys; i++) all[i] = i;
-  if (int rc = lists.set(hs, all, lanes, nc == 2 ? 16 : 64, s)) return rc;  // synchronises
+  if (int rc = lists.set(hs, all, lanes, nc == 2 ? 32 : 64, s)) return rc;  // synchronises
   if (prec == 64)
     DST_HIP(nc == 2 ? (launch_g_spmv<double, 2, 0>(lanes, dS, lists.w, lists.nw, 0, s))
                     : (launch_g_spmv<double, 4, 0>(lanes, dS, lists.w, lists.nw, 0, s)));

@@ -105,6 +105,12 @@ int64_t total_blocks(const dirac_st_problem *p);
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Optional timing of selected kernels with HIP events recorded around their
+// launches on the launch stream (off unless dirac_st_timing(1) was called).
+// kt_start returns a token (-1 when timing is off); kt_stop closes it.
+int kt_start(int kind, hipStream_t s);
+void kt_stop(int token, hipStream_t s);
+
 // Rows handled by one XCD stay contiguous: hardware dispatches workgroup b to
 // XCD b % 8, so logical tile = position inside that XCD's share.
 __device__ inline int64_t xcd_tile(int64_t b, int64_t nwg) {

@@ -90,6 +90,8 @@ _lib.dirac_st_spmv_batched_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_spmv_batched.argtypes = [_i32, C.POINTER(_BSRP), _i32, C.POINTER(_vp), C.POINTER(_vp), _i32,
                                        _vp, C.c_size_t, _vp]
 _lib.dirac_st_time_eigen.argtypes = [_i32, C.c_double, _vp, _vp, _vp]
+_lib.dirac_st_timing.argtypes = [_i32]
+_lib.dirac_st_timing_read.argtypes = [_i32, C.POINTER(_i64), C.POINTER(C.c_double)]
 _lib.dirac_st_batched_set_lanes.argtypes = [_i32, _i32, _i32]
 _lib.dirac_st_batched_lanes.argtypes = [_i32, _i32, _i64]
 _lib.dirac_st_batched_lanes.restype = _i32
@@ -100,7 +102,8 @@ EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_
            "dirac_st_nn_forward", "dirac_st_nn_backward", "dirac_st_nn_train_step",
            "dirac_st_fgmres_nn", "dirac_st_batched_workspace_bytes", "dirac_st_fgmres_batched",
            "dirac_st_spmv_batched_workspace_bytes", "dirac_st_spmv_batched",
-           "dirac_st_batched_set_lanes", "dirac_st_batched_lanes", "dirac_st_time_eigen"]
+           "dirac_st_batched_set_lanes", "dirac_st_batched_lanes", "dirac_st_time_eigen",
+           "dirac_st_timing", "dirac_st_timing_read"]
 
 
 class DiracError(RuntimeError):
@@ -413,7 +416,7 @@ def spmv_batched(ops, xs, ys=None, lanes=None, work=None):
     if ys is None:
         ys = [torch.empty_like(x) for x in xs]
     if lanes is None:
-        lanes = 16 if ops[0].nc == 2 else 64
+        lanes = (32 if prec == 64 else 16) if ops[0].nc == 2 else 64
     nbytes = int(_lib.dirac_st_spmv_batched_workspace_bytes(len(ops)))
     if nbytes == 0:
         raise DiracError(EINVAL, last_error())
@@ -441,3 +444,18 @@ def time_eigen(nt: int, ht: float):
     Q = np.zeros((nt, nt), np.complex128)
     _check(_lib.dirac_st_time_eigen(nt, ht, lam.ctypes.data, W.ctypes.data, Q.ctypes.data))
     return lam, W, Q
+
+
+TIMED = {"spmv64": 0, "spmv32": 1, "resid64": 2, "assemble": 3}
+
+
+def timing(on: bool) -> None:
+    """dirac_st_timing: start (clearing earlier records) or stop kernel timing."""
+    _check(_lib.dirac_st_timing(1 if on else 0))
+
+
+def timing_read(kind: str):
+    """dirac_st_timing_read: (launch count, total ms) of one timed kernel."""
+    n, ms = _i64(0), C.c_double(0.0)
+    _check(_lib.dirac_st_timing_read(TIMED[kind], C.byref(n), C.byref(ms)))
+    return int(n.value), float(ms.value)

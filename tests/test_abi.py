@@ -104,3 +104,15 @@ def test_time_eigen_rejects_bad_sizes():
     for nt, ht in ((0, 0.1), (2049, 1e-3), (4, -1.0)):
         with pytest.raises(D.DiracError):
             D.time_eigen(nt, ht)
+
+
+def test_kernel_timers_host_side():
+    """The timing switch and read-out are host-only: with nothing launched the
+    counts are zero; an unknown kernel kind is rejected."""
+    from paper_2103_14588_amd import dirac_st as D
+    D.timing(True)
+    for k in D.TIMED:
+        assert D.timing_read(k) == (0, 0.0)
+    D.timing(False)
+    with pytest.raises(D.DiracError):
+        D._check(D._lib.dirac_st_timing_read(99, D.C.byref(D._i64(0)), D.C.byref(D.C.c_double(0.0))))

@@ -18,7 +18,7 @@ from paper_2103_14588_amd import inputs as IN
 pytestmark = pytest.mark.gpu
 
 MESHES = [[4, 9, 10], [6, 12, 11], [5, 17, 9], [7, 8, 8], [3, 5, 4]]
-LANES = {(2, 64): [4, 8, 16], (2, 32): [4, 8, 16], (4, 64): [64], (4, 32): [32, 64]}
+LANES = {(2, 64): [4, 8, 16, 32], (2, 32): [4, 8, 16, 32], (4, 64): [64], (4, 32): [32, 64]}
 
 
 @pytest.fixture(scope="module")
@@ -94,7 +94,7 @@ def test_spmv_batched_rejects_bad_lanes(D):
     op, _ = D.assemble(IN.Spec(d=2, n=[3, 4, 5]), None)
     x = torch.zeros(op.n, dtype=torch.complex128, device="cuda")
     with pytest.raises(D.DiracError):
-        D.spmv_batched([op], [x], lanes=32)
+        D.spmv_batched([op], [x], lanes=12)
 
 
 @pytest.mark.parametrize("precision", [64, 32])
@@ -218,9 +218,9 @@ def test_full_size_batch_sampled_rows(D):
     ops = [D.assemble(w.spec, None, fp32=True, block_jacobi=False)[0] for w in wls]
     gen = torch.Generator(device="cuda").manual_seed(4)
     xs = [torch.randn(op.n, dtype=torch.complex128, device="cuda", generator=gen) for op in ops]
-    ys = D.spmv_batched(ops, xs, lanes=16)
+    ys = D.spmv_batched(ops, xs, lanes=32)
     xs32 = [x.to(torch.complex64) for x in xs]
-    ys32 = D.spmv_batched(ops, xs32, lanes=8)
+    ys32 = D.spmv_batched(ops, xs32, lanes=16)
     rng = np.random.default_rng(5)
     for w, op, x, y, x32, y32 in zip(wls, ops, xs, ys, xs32, ys32):
         p = oprob(w.spec)

@@ -255,3 +255,21 @@ def test_full_size_sampled_rows(D, wl):
         want32 = np.einsum("kij,kj->i", blocks.astype(np.complex64).astype(np.complex128), xs32)
         got32 = y32[r * nc:(r + 1) * nc].cpu().numpy()
         assert np.abs(got32 - want32).max() <= 1e-5 * np.abs(blocks).max() * np.abs(xs32).max() * len(cols)
+
+
+def test_kernel_timers_count_solver_launches(D):
+    """HIP-event timers inside the library: a GMRES solve from x = 0 that takes
+    k Arnoldi steps records k product SpMVs and one residual SpMV per restart
+    after the first; the assembly kernel is recorded once per assembly."""
+    spec = IN.Spec(d=2, n=[6, 17, 9], lens=[1.0, 0.9, 1.1], m=0.7)
+    psi = IN.gaussian_packet(spec, [0.4, 0.5], [3.0, 1.0], 0.2, np.ones(2) / np.sqrt(2))
+    D.timing(True)
+    op, b = D.assemble(spec, dev(psi))
+    x, info = D.gmres(op, b, restart=5, max_it=23, rtol=1e-14, pc="bj")
+    n_spmv, ms_spmv = D.timing_read("spmv64")
+    n_res, _ = D.timing_read("resid64")
+    n_asm, ms_asm = D.timing_read("assemble")
+    D.timing(False)
+    assert n_asm == 1 and ms_asm > 0.0
+    assert n_spmv == info["iters"] and ms_spmv > 0.0
+    assert n_res == info["cycles"]  # one residual after each cycle, none before the first
