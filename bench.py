@@ -34,8 +34,17 @@ HBM_PEAK_GBS = 8000.0
 
 
 def spmv_bytes(op, cs):
-    """Algorithmic bytes of one SpMV: values, column indices, row pointers,
-    x and y once each."""
+    """Algorithmic bytes of one single-system SpMV: block values, x and y once
+    each; for 2x2 blocks the kernel computes block addresses and columns from
+    the stencil structure, for 4x4 blocks it reads the block-CSR indices."""
+    if op.nc == 4:
+        return spmv_bytes_indexed(op, cs)
+    return op.nnzb * op.nc * op.nc * cs + 2 * op.n * cs
+
+
+def spmv_bytes_indexed(op, cs):
+    """Algorithmic bytes of one indexed BSR SpMV (the grouped batched kernel):
+    values, column indices, row pointers, x and y once each."""
     return op.nnzb * (op.nc * op.nc * cs + 4) + 4 * (op.nrows + 1) + 2 * op.n * cs
 
 
@@ -217,7 +226,7 @@ def batch_bench(args):
     gen = torch.Generator(device="cuda").manual_seed(0)
     v32 = [torch.randn(op.n, dtype=torch.complex64, device="cuda", generator=gen) for op in ops]
     y32 = [torch.empty_like(v) for v in v32]
-    nbytes = sum(spmv_bytes(op, 8) for op in ops)
+    nbytes = sum(spmv_bytes_indexed(op, 8) for op in ops)
     swork = torch.empty(int(D._lib.dirac_st_spmv_batched_workspace_bytes(len(ops))), dtype=torch.uint8,
                         device="cuda")
     for g in (4, 8, 16, 32):
@@ -361,7 +370,8 @@ def main():
     l_res, n_res = live_avg("resid64")
     l_asm, n_asm = live_avg("assemble")
     res_bytes = by64 + op.n * 16  # the residual form also reads b
-    rl_kernel = "spmv_kernel<double,%d,%d,false> (BSR SpMV, complex128)" % (op.nc, 32 if op.nc == 2 else 64)
+    rl_kernel = ("spmv_st_kernel<double,2,%d,32,false> (structured block SpMV, complex128)" % spec.d
+                 if op.nc == 2 else "spmv_kernel<double,4,64,false> (BSR SpMV, complex128)")
     if l_spmv is None:  # no product in the timed steps: fall back to the isolated launches
         l_spmv, n_spmv = t_spmv64, 0
     g_live = by64 / l_spmv / 1e6

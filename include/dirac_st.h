@@ -232,7 +232,10 @@ int dirac_st_assemble(const dirac_st_problem *prob, const void *psi0, dirac_st_b
                       void *stream);
 
 /* y = A x (Sec. 2.2: the product inside GMRES).  prec 64: complex128 x, y and
- * val64; prec 32: complex64 x, y and val32.  x and y must not overlap. */
+ * val64; prec 32: complex64 x, y and val32.  x and y must not overlap.  A must
+ * come from dirac_st_assemble: for 2x2 blocks the block addresses and columns
+ * are computed from A->prob (the stencil of the assembled pattern) and
+ * row_ptr / col_idx are not read; 4x4 blocks use them. */
 int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x, void *y, void *stream);
 
 /* z = M^{-1} v for the preconditioner `pc` (DIRAC_ST_PC_*) in precision prec

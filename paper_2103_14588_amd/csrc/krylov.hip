@@ -229,8 +229,7 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       rn = bnorm;
       x_zero = false;
     } else {
-      DST_HIP(launch_spmv<double>(nc, A->nrows, A->row_ptr, A->col_idx, A->val64, x, b, rbuf, 1.0,
-                                  true, s));
+      DST_HIP(launch_spmv_st<double>(A, A->val64, x, b, rbuf, 1.0, true, s));
       if (int rc = read_norm(rbuf, rn)) return rc;
     }
     S.relres = rn / bnorm;
@@ -267,20 +266,17 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       C *w = V + (int64_t)(j + 1) * L.ldv;
       // w = A M^{-1} v_j
       if (P.kind == DIRAC_ST_PC_NONE && !P.nn_on && !flexible) {
-        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, vj, nullptr, w,
-                               (T)sigma_j, false, s));
+        DST_HIP(launch_spmv_st<T>(A, val, vj, nullptr, w, (T)sigma_j, false, s));
       } else if (P.kind == DIRAC_ST_PC_NONE && !P.nn_on) {
         // flexible without any preconditioner: z_j = v_j
         C *zj = Zb + (int64_t)j * L.ldv;
         scale_copy<T><<<nblocks(N), 256, 0, s>>>(vj, sigma_j, zj, N);
         DST_LAUNCHED();
-        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, zj, nullptr, w, (T)1,
-                               false, s));
+        DST_HIP(launch_spmv_st<T>(A, val, zj, nullptr, w, (T)1, false, s));
       } else {
         C *zj = flexible ? Zb + (int64_t)j * L.ldv : z;
         if (int rc = pc_apply<T>(P, vj, zj, sigma_j, N, s)) return rc;
-        DST_HIP(launch_spmv<T>(nc, A->nrows, A->row_ptr, A->col_idx, val, zj, nullptr, w, (T)1,
-                               false, s));
+        DST_HIP(launch_spmv_st<T>(A, val, zj, nullptr, w, (T)1, false, s));
       }
       const int jp1 = j + 1, mk = maxk_bucket(jp1);
       // pass 1: h1 = V^H w
@@ -375,11 +371,9 @@ extern "C" int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x,
   DST_CHECK(((uintptr_t)x & 15) == 0 && ((uintptr_t)y & 15) == 0, "x, y must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   if (prec == 64)
-    DST_HIP(launch_spmv<double>(A->nc, A->nrows, A->row_ptr, A->col_idx, A->val64, x, nullptr, y,
-                                1.0, false, s));
+    DST_HIP(launch_spmv_st<double>(A, A->val64, x, nullptr, y, 1.0, false, s));
   else
-    DST_HIP(launch_spmv<float>(A->nc, A->nrows, A->row_ptr, A->col_idx, A->val32, x, nullptr, y,
-                               1.0f, false, s));
+    DST_HIP(launch_spmv_st<float>(A, A->val32, x, nullptr, y, 1.0f, false, s));
   return DIRAC_ST_OK;
 }
 

@@ -110,6 +110,158 @@ __device__ __forceinline__ void spmv_tile(int64_t tile, int64_t nrows, const int
   }
 }
 
+// Block-row structure of the assembled operator, used to address blocks and
+// columns without reading row_ptr / col_idx.  A row (time node tau = 1..n_t,
+// spatial node with coordinates i_a) couples to the 3^d spatial neighbours
+// (periodic) in each of the time nodes tau-1 (if tau >= 2), tau, tau+1 (if
+// tau <= n_t - 1); its blocks are stored in ascending column order.
+struct Stencil {
+  int d, nt;
+  int n[4];    // n[1..d] spatial nodes per axis
+  int64_t S;   // spatial nodes
+  int P;       // 3^d
+};
+
+inline Stencil make_stencil(const dirac_st_problem *p) {
+  Stencil g{};
+  g.d = p->d;
+  g.nt = p->n[0];
+  g.S = 1;
+  g.P = 1;
+  for (int a = 1; a <= 3; a++) g.n[a] = a <= p->d ? p->n[a] : 1;
+  for (int a = 1; a <= p->d; a++) {
+    g.S *= p->n[a];
+    g.P *= 3;
+  }
+  return g;
+}
+
+// coordinate of sorted neighbour k (0, 1, 2) of i on a periodic axis of n >= 3
+// nodes: the set {i-1, i, i+1} mod n in ascending order
+__device__ __forceinline__ int nb_coord(int i, int n, int k) {
+  if (i == 0) return k == 2 ? n - 1 : k;
+  if (i == n - 1) return k == 0 ? 0 : n - 3 + k;
+  return i - 1 + k;
+}
+
+// first block and block count of a row
+template <int DS>
+__device__ __forceinline__ void st_row(const Stencil &g, int64_t row, int64_t &rs, int &nb) {
+  const int tau = (int)(row / g.S) + 1;
+  const int64_t s = row - (int64_t)(tau - 1) * g.S;
+  const int P = g.P;
+  if (g.nt == 1) {
+    rs = row * P;
+    nb = P;
+    return;
+  }
+  const int mid = 3 * P, edge = 2 * P;
+  if (tau == 1) {
+    rs = s * edge;
+  } else {
+    rs = g.S * edge + (int64_t)(tau - 2) * g.S * mid + s * (tau == g.nt ? edge : mid);
+  }
+  nb = (tau == 1 || tau == g.nt) ? edge : mid;
+}
+
+// spmv_tile without index traffic: same work split and value stream as
+// spmv_tile, block range and columns computed from the stencil
+template <typename T, int NC, int DS, int G, bool RESID>
+__device__ __forceinline__ void spmv_tile_st(int64_t tile, int64_t nrows, const Stencil &g,
+                                             const cx<T> *__restrict__ val, const cx<T> *__restrict__ x,
+                                             const cx<T> *__restrict__ bvec, cx<T> *__restrict__ y, T alpha) {
+  using Ch = typename chunk_of<T>::type;
+  constexpr int J = chunk_of<T>::J;
+  constexpr int IB = NC / J;
+  constexpr int CPB = NC * NC / J;
+  constexpr int BPI = G / CPB;
+  constexpr int RPW = 256 / G;
+  constexpr int IMASK = (NC - 1) * IB;
+  static_assert(G % CPB == 0 && G <= 64, "group must hold whole blocks");
+  const int lane = threadIdx.x % G;
+  const int64_t row = tile * RPW + threadIdx.x / G;
+  const int i = (lane / IB) % NC;
+  const int jc = lane % IB;
+  const int bofs = lane / CPB;
+  constexpr int MAXB = NC == 2 ? 27 : 81;
+  constexpr int MAXIT = (MAXB + BPI - 1) / BPI;
+  constexpr int UNR = MAXIT < 8 ? MAXIT : 8;
+  cx<T> acc = mk<cx<T>>(0, 0);
+  if (row < nrows) {
+    int64_t rs;
+    int nb;
+    st_row<DS>(g, row, rs, nb);
+    const int tau = (int)(row / g.S) + 1;
+    int64_t sr = row - (int64_t)(tau - 1) * g.S;
+    // per axis: element offsets (in x, nc-blocks) of the three sorted
+    // neighbours; per block only digit extraction by constants and selects
+    constexpr int P = DS == 1 ? 3 : DS == 2 ? 9 : 27;
+    int off[DS + 1][3];
+    int stride = 1;
+#pragma unroll
+    for (int a = 1; a <= DS; a++) {
+      const int n = g.n[a];
+      const int ia = (int)(sr % n);
+      sr /= n;
+#pragma unroll
+      for (int k = 0; k < 3; k++) off[a][k] = nb_coord(ia, n, k) * stride;
+      stride *= n;
+    }
+    const int64_t tbase = (int64_t)((tau >= 2 ? tau - 1 : tau) - 1) * g.S;
+    const Ch *vbase = reinterpret_cast<const Ch *>(val + rs * NC * NC + i * NC + jc * J);
+    for (int b0 = bofs; b0 < nb; b0 += UNR * BPI) {
+      Ch v[UNR], xv[UNR];
+#pragma unroll
+      for (int it = 0; it < UNR; it++) {
+        const int b = b0 + it * BPI;
+        if (b < nb) {
+          if constexpr (sizeof(T) == 8) v[it] = __builtin_nontemporal_load(vbase + (int64_t)b * (NC * NC / J));
+          else v[it] = vbase[(int64_t)b * (NC * NC / J)];
+          const int kt = b / P;
+          int rem = b - kt * P;
+          int64_t c = tbase + (int64_t)kt * g.S;
+#pragma unroll
+          for (int a = 1; a <= DS; a++) {
+            const int k = rem % 3;
+            rem /= 3;
+            c += k == 0 ? off[a][0] : (k == 1 ? off[a][1] : off[a][2]);
+          }
+          xv[it] = *reinterpret_cast<const Ch *>(x + c * NC + jc * J);
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < UNR; it++) {
+        const int b = b0 + it * BPI;
+        if (b < nb) acc = chunk_mac<T>(acc, v[it], xv[it]);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    if (off & IMASK) continue;
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+  }
+  if (row < nrows && lane == i * IB) {
+    const int64_t o = row * NC + i;
+    if (RESID) {
+      cx<T> bb = bvec[o];
+      y[o] = mk<cx<T>>(bb.x - acc.x, bb.y - acc.y);
+    } else {
+      y[o] = mk<cx<T>>(alpha * acc.x, alpha * acc.y);
+    }
+  }
+}
+
+template <typename T, int NC, int DS, int G, bool RESID>
+__global__ __launch_bounds__(256) void spmv_st_kernel(int64_t nrows, int64_t nwg, Stencil g,
+                                                      const cx<T> *__restrict__ val,
+                                                      const cx<T> *__restrict__ x,
+                                                      const cx<T> *__restrict__ bvec,
+                                                      cx<T> *__restrict__ y, T alpha) {
+  spmv_tile_st<T, NC, DS, G, RESID>(xcd_tile(blockIdx.x, nwg), nrows, g, val, x, bvec, y, alpha);
+}
+
 template <typename T, int NC, int G, bool RESID>
 __global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, int64_t nwg,
                                                    const int32_t *__restrict__ rp,
@@ -144,6 +296,34 @@ inline hipError_t launch_spmv(int nc, int64_t nrows, const int32_t *rp, const in
   }
   constexpr int G4 = dbl ? 64 : 32;
   return resid ? go(spmv_kernel<T, 4, G4, true>, G4) : go(spmv_kernel<T, 4, G4, false>, G4);
+}
+
+// Host launcher for an operator built by dirac_st_assemble.  2x2 blocks use
+// the structured kernel (no index traffic; measured 2 % faster in complex128
+// and 20 % faster in complex64 than the indexed kernel at 2+1D 128^3); 4x4
+// blocks keep the indexed kernel (its 16 lanes per block would all repeat the
+// column arithmetic; 9 % slower structured at 3+1D 32^4).
+template <typename T>
+inline hipError_t launch_spmv_st(const dirac_st_bsr *A, const void *val, const void *x, const void *bvec,
+                                 void *y, T alpha, bool resid, hipStream_t st) {
+  if (A->nc == 4)
+    return launch_spmv<T>(A->nc, A->nrows, A->row_ptr, A->col_idx, val, x, bvec, y, alpha, resid, st);
+  const Stencil g = make_stencil(&A->prob);
+  const int64_t nrows = A->nrows;
+  auto go = [&](auto kern, int G) {
+    const int64_t rpw = 256 / G;
+    const int64_t nwg = (nrows + rpw - 1) / rpw;
+    const int tk = kt_start(resid ? DIRAC_ST_TIMED_RESID64
+                                  : (sizeof(T) == 8 ? DIRAC_ST_TIMED_SPMV64 : DIRAC_ST_TIMED_SPMV32), st);
+    kern<<<(unsigned)nwg, 256, 0, st>>>(nrows, nwg, g, (const cx<T> *)val, (const cx<T> *)x,
+                                        (const cx<T> *)bvec, (cx<T> *)y, alpha);
+    kt_stop(tk, st);
+    return hipGetLastError();
+  };
+  constexpr int G2 = sizeof(T) == 8 ? 32 : 16;
+  if (g.d == 1)
+    return resid ? go(spmv_st_kernel<T, 2, 1, G2, true>, G2) : go(spmv_st_kernel<T, 2, 1, G2, false>, G2);
+  return resid ? go(spmv_st_kernel<T, 2, 2, G2, true>, G2) : go(spmv_st_kernel<T, 2, 2, G2, false>, G2);
 }
 
 }  // namespace dst
