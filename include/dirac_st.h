@@ -337,7 +337,9 @@ int dirac_st_fgmres_batched(int32_t nsys, const dirac_st_bsr *const *A, const vo
 /* Host.  Workspace bytes of dirac_st_spmv_batched (0 if nsys is out of range). */
 size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys);
 
-/* y[i] = A[i] x[i] for every system in one launch (Sec. 2.2 product).  A, x, y:
+/* y[i] = A[i] x[i] for every system in one launch (Sec. 2.2 product; like
+ * dirac_st_spmv, 2x2-block operators are addressed through their stencil and
+ * must come from dirac_st_assemble).  A, x, y:
  * host arrays of nsys pointers; x[i], y[i] device vectors of complex128
  * (prec 64, val64) or complex64 (prec 32, val32).  lanes: lanes per block row,
  * 4, 8, 16 or 32 for nc = 2; 64 (or 32 at prec 32) for nc = 4.  Enqueues only

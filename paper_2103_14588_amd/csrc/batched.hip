@@ -45,6 +45,7 @@ struct BSys {
   Ctrl *ctrl;
   int nc, k;     // block size; steps of the current cycle (set before updates)
   int64_t lt[4]; // line preconditioner workgroups: time transform, axis 2, axis 3, line solve
+  Stencil st;    // block-row structure (2x2 blocks: the SpMV reads no indices)
 };
 
 // Line preconditioner of one system (device copy; pointers at the working precision).
@@ -98,12 +99,21 @@ __global__ __launch_bounds__(256) void g_spmv(const BSys *__restrict__ S, WorkLi
   if (MODE == 0) {
     const cx<T> *z = (const cx<T> *)s.Z + (int64_t)j * s.ldv;
     cx<T> *w = (cx<T> *)s.V + (int64_t)(j + 1) * s.ldv;
-    spmv_tile<T, NC, G, false>(tile, s.nrows, s.rp, s.ci,
-                               (const cx<T> *)(sizeof(T) == 8 ? s.val64 : s.val32), z, nullptr, w,
-                               (T)1);
+    const cx<T> *val = (const cx<T> *)(sizeof(T) == 8 ? s.val64 : s.val32);
+    if constexpr (NC == 2) {
+      if (s.st.d == 1) spmv_tile_st<T, 2, 1, G, false>(tile, s.nrows, s.st, val, z, nullptr, w, (T)1);
+      else spmv_tile_st<T, 2, 2, G, false>(tile, s.nrows, s.st, val, z, nullptr, w, (T)1);
+    } else {
+      spmv_tile<T, NC, G, false>(tile, s.nrows, s.rp, s.ci, val, z, nullptr, w, (T)1);
+    }
   } else {
-    spmv_tile<double, NC, G, true>(tile, s.nrows, s.rp, s.ci, (const double2 *)s.val64, s.x, s.b,
-                                   s.r64, 1.0);
+    const double2 *val = (const double2 *)s.val64;
+    if constexpr (NC == 2) {
+      if (s.st.d == 1) spmv_tile_st<double, 2, 1, G, true>(tile, s.nrows, s.st, val, s.x, s.b, s.r64, 1.0);
+      else spmv_tile_st<double, 2, 2, G, true>(tile, s.nrows, s.st, val, s.x, s.b, s.r64, 1.0);
+    } else {
+      spmv_tile<double, NC, G, true>(tile, s.nrows, s.rp, s.ci, val, s.x, s.b, s.r64, 1.0);
+    }
   }
 }
 
@@ -549,6 +559,7 @@ static void fill_desc(BSys &q, const dirac_st_bsr *A) {
   q.n = A->nrows * A->nc;
   q.nblk = (q.n + 255) / 256;
   q.nc = A->nc;
+  q.st = make_stencil(&A->prob);
 }
 
 template <typename T>

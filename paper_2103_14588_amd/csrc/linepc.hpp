@@ -350,6 +350,114 @@ __device__ __forceinline__ void blk_apply(const cx<T> (&m)[NC * NC], const cx<T>
   }
 }
 
+// In-place periodic block-tridiagonal solve along x for line l (nodes
+// l * n1 .. l * n1 + n1 - 1, nc components each), one thread per line with
+// no cooperation: each sweep loads the next node's factors and values one
+// step ahead, so the loads overlap the dependent arithmetic of the current
+// node.  Used when there are too few lines for the LDS-staged workgroup
+// version to fill the chip.
+template <typename T, int NC>
+__device__ __forceinline__ void line_solve_thread(const cx<T> *__restrict__ fac, const cx<T> *__restrict__ lined,
+                                               cx<T> *__restrict__ X, int n1, int64_t lines, int64_t l) {
+  constexpr int B = NC * NC;
+  using C = cx<T>;
+  C *x = X + l * n1 * NC;
+  auto fb = [&](int i, int slot) { return ((int64_t)i * 4 * B + slot * B) * lines + l; };
+  C y[NC], t[NC], v[NC], vn[NC];
+  C Gm[B], Km[B], Gn[B], Kn[B];
+#pragma unroll
+  for (int c = 0; c < NC; c++) y[c] = vn[c] = mk<C>(0, 0);
+#pragma unroll
+  for (int q = 0; q < B; q++) Gn[q] = Kn[q] = mk<C>(0, 0);
+  // forward: y_i = G_i v_i - K_i y_{i-1}
+  blk_load<T, NC>(fac, fb(0, 0), lines, Gm);
+  blk_load<T, NC>(fac, fb(0, 1), lines, Km);
+#pragma unroll
+  for (int c = 0; c < NC; c++) v[c] = x[c];
+  for (int i = 0; i < n1 - 1; i++) {
+    if (i + 1 < n1 - 1) {
+      blk_load<T, NC>(fac, fb(i + 1, 0), lines, Gn);
+      blk_load<T, NC>(fac, fb(i + 1, 1), lines, Kn);
+#pragma unroll
+      for (int c = 0; c < NC; c++) vn[c] = x[(i + 1) * NC + c];
+    }
+    blk_apply<T, NC>(Gm, v, t, false, false);
+    blk_apply<T, NC>(Km, y, t, true, true);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      y[c] = t[c];
+      x[i * NC + c] = t[c];
+    }
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      Gm[q] = Gn[q];
+      Km[q] = Kn[q];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = vn[c];
+  }
+  // backward: a_i = y_i - E_i a_{i+1}
+  C alast[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) alast[c] = y[c];
+  if (n1 >= 3) {
+    blk_load<T, NC>(fac, fb(n1 - 3, 2), lines, Gm);
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = x[(n1 - 3) * NC + c];
+  }
+  for (int i = n1 - 3; i >= 0; i--) {
+    if (i > 0) {
+      blk_load<T, NC>(fac, fb(i - 1, 2), lines, Gn);
+#pragma unroll
+      for (int c = 0; c < NC; c++) vn[c] = x[(i - 1) * NC + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) t[c] = v[c];
+    blk_apply<T, NC>(Gm, y, t, true, true);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      y[c] = t[c];
+      x[i * NC + c] = t[c];
+    }
+#pragma unroll
+    for (int q = 0; q < B; q++) Gm[q] = Gn[q];
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = vn[c];
+  }
+  // last node: S^{-1} (v_{n-1} - L_{n-1} a_{n-2} - U_{n-1} a_0)
+#pragma unroll
+  for (int c = 0; c < NC; c++) t[c] = x[(n1 - 1) * NC + c];
+  blk_load<T, NC>(lined, 0 * B * lines + l, lines, Gm);
+  blk_apply<T, NC>(Gm, alast, t, true, true);
+  blk_load<T, NC>(lined, 1 * B * lines + l, lines, Gm);
+  blk_apply<T, NC>(Gm, y, t, true, true);
+  C xl[NC];
+  blk_load<T, NC>(lined, 2 * B * lines + l, lines, Gm);
+  blk_apply<T, NC>(Gm, t, xl, false, false);
+#pragma unroll
+  for (int c = 0; c < NC; c++) x[(n1 - 1) * NC + c] = xl[c];
+  // x_i = a_i + H_i x_{n-1}
+  blk_load<T, NC>(fac, fb(0, 3), lines, Gm);
+#pragma unroll
+  for (int c = 0; c < NC; c++) v[c] = x[c];
+  for (int i = 0; i < n1 - 1; i++) {
+    if (i + 1 < n1 - 1) {
+      blk_load<T, NC>(fac, fb(i + 1, 3), lines, Gn);
+#pragma unroll
+      for (int c = 0; c < NC; c++) vn[c] = x[(i + 1) * NC + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) t[c] = v[c];
+    blk_apply<T, NC>(Gm, xl, t, true, false);
+#pragma unroll
+    for (int c = 0; c < NC; c++) x[i * NC + c] = t[c];
+#pragma unroll
+    for (int q = 0; q < B; q++) Gm[q] = Gn[q];
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = vn[c];
+  }
+}
+
 // In-place periodic block-tridiagonal solve along x for the 64 lines
 // l0 .. l0 + 63 of one workgroup (line l holds nodes l * n1 .. l * n1 + n1 - 1,
 // nc components each); thread t owns line l0 + t.  The line values move
@@ -491,6 +599,17 @@ __global__ __launch_bounds__(64) void line_solve(const cx<T> *__restrict__ fac,
                                                  cx<T> *__restrict__ X, int n1, int64_t lines) {
   line_solve_wg<T, NC, kLineChunk>(fac, lined, X, n1, lines, (int64_t)blockIdx.x * 64);
 }
+
+template <typename T, int NC>
+__global__ __launch_bounds__(64) void line_solve_pt(const cx<T> *__restrict__ fac,
+                                                    const cx<T> *__restrict__ lined,
+                                                    cx<T> *__restrict__ X, int n1, int64_t lines) {
+  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (l < lines) line_solve_thread<T, NC>(fac, lined, X, n1, lines, l);
+}
+
+// below this many lines a single system's solve runs one thread per line
+constexpr int64_t kLineStagedMin = 65536;
 
 static __global__ void zero_i32_flag(int *f) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *f = 0;

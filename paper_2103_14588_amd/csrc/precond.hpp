@@ -383,10 +383,14 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
     }
     const unsigned gl = (unsigned)((L.lines + 63) / 64);
     const cx<T> *fac = (const cx<T> *)(P.line + L.fac), *lined = (const cx<T> *)(P.line + L.lined);
-    if (G.nc == 2)
-      line_solve<T, 2><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
-    else
-      line_solve<T, 4><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
+    const bool staged = L.lines >= kLineStagedMin;
+    if (G.nc == 2) {
+      if (staged) line_solve<T, 2><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
+      else line_solve_pt<T, 2><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
+    } else {
+      if (staged) line_solve<T, 4><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
+      else line_solve_pt<T, 4><<<gl, 64, 0, s>>>(fac, lined, cur, G.n[1], L.lines);
+    }
     DST_LAUNCHED();
     for (int a = 2; a <= G.d; a++) {
       if (int rc = transverse(a, true, cur, oth)) return rc;

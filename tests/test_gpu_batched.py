@@ -67,8 +67,8 @@ def assemble_all(D, specs, seed=0):
 @pytest.mark.parametrize("nc,prec", sorted(LANES))
 def test_spmv_batched_matches_oracle(D, nc, prec):
     if nc == 2:
-        specs = klein_specs(MESHES, 1) + [IN.Spec(d=1, n=[7, 37])]
-        specs = specs[:5]
+        # 2x2 blocks of both dimensions in one grouped launch
+        specs = klein_specs(MESHES, 1)[:4] + [IN.Spec(d=1, n=[7, 37]), IN.Spec(d=1, n=[1, 5])]
     else:
         specs = [IN.Spec(d=3, n=[4, 5, 3, 6]), IN.Spec(d=3, n=[3, 4, 4, 3], vkind=1, v0=1.0, x0=0.3),
                  IN.Spec(d=3, n=[5, 3, 4, 4])]
