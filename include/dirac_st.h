@@ -334,8 +334,9 @@ int dirac_st_fgmres_batched(int32_t nsys, const dirac_st_bsr *const *A, const vo
                             void *const *x, const dirac_st_opts *opts, void *work, size_t work_bytes,
                             dirac_st_stats *stats, void *stream);
 
-/* Host.  Workspace bytes of dirac_st_spmv_batched (0 if nsys is out of range). */
-size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys);
+/* Host.  Workspace bytes of dirac_st_spmv_batched for these systems (0 on
+ * invalid input). */
+size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys, const dirac_st_bsr *const *A);
 
 /* y[i] = A[i] x[i] for every system in one launch (Sec. 2.2 product; like
  * dirac_st_spmv, 2x2-block operators are addressed through their stencil and

@@ -61,33 +61,35 @@ struct LineJob {
 constexpr int kMaxBatch = DIRAC_ST_MAX_BATCH;
 
 // Work lists of one launch: the grid's workgroups are numbered 0..off[nact]-1
-// and system act[a] owns workgroups [off[a], off[a+1]).  The offsets are
-// staged in LDS and searched by bisection; the XCD-aware renumbering keeps the
-// tiles an XCD processes contiguous (one system's rows share that XCD's L2).
+// and system act[a] owns workgroups [off[a], off[a+1]).  tab[w] = a for every
+// workgroup w (filled on the device whenever the list changes), so a
+// workgroup finds its system with two scalar loads.  The XCD-aware
+// renumbering keeps the tiles an XCD processes contiguous (one system's rows
+// share that XCD's L2).
 struct WorkList {
-  const int64_t *act;  // active systems
-  const int64_t *off;  // nact + 1 prefix sums of workgroups per system
+  const int64_t *act;   // active systems
+  const int64_t *off;   // nact + 1 prefix sums of workgroups per system
+  const uint16_t *tab;  // position in act of each workgroup's system
   int nact;
 };
 
-__device__ inline int find_sys(const WorkList &L, int64_t &local) {
-  __shared__ int64_t so[kMaxBatch + 1];
-  for (int i = threadIdx.x; i <= L.nact; i += blockDim.x) so[i] = L.off[i];
-  __syncthreads();
+__device__ __forceinline__ int find_sys(const WorkList &L, int64_t &local) {
   const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
-  int lo = 0, hi = L.nact;  // so[lo] <= bid < so[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (so[mid] <= bid) lo = mid;
-    else hi = mid;
-  }
   // every lane holds the same values: make that visible to the compiler so
   // the descriptor fields and everything derived from them stay scalar
-  const int64_t loc = bid - so[lo];
+  const int a = __builtin_amdgcn_readfirstlane((int)L.tab[bid]);
+  const int64_t loc = bid - L.off[a];
   const int lo32 = __builtin_amdgcn_readfirstlane((int)(uint32_t)(loc & 0xffffffff));
   const int hi32 = __builtin_amdgcn_readfirstlane((int)(loc >> 32));
   local = ((int64_t)hi32 << 32) | (uint32_t)lo32;
-  return __builtin_amdgcn_readfirstlane((int)L.act[lo]);
+  return __builtin_amdgcn_readfirstlane((int)L.act[a]);
+}
+
+// tab[off[a] .. off[a+1]) = a, one workgroup per listed system
+__global__ __launch_bounds__(256) void g_fill_tab(const int64_t *__restrict__ off, uint16_t *__restrict__ tab) {
+  const int a = blockIdx.x;
+  const int64_t e0 = off[a], e1 = off[a + 1];
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) tab[e] = (uint16_t)a;
 }
 
 // ------------------------------------------------------------ grouped kernels
@@ -353,8 +355,12 @@ constexpr int kListArrays = 8;
 struct BatchLayout {
   std::vector<size_t> V, Z, r64, partial, ctrl, spec;
   std::vector<int64_t> ldv, nblk;
-  size_t desc, jobs, sjobs, lists, gather, total;
+  size_t desc, jobs, sjobs, lists, gather, tab_w, tab_r, tab_v, tab_l, total;
+  int64_t cap_rows, cap_vec, cap_lines;  // workgroup-table capacities
 };
+
+// fewest block rows one SpMV workgroup may cover (largest lane count)
+static int64_t rows_per_wg_min(int nc) { return nc == 2 ? 256 / 32 : 256 / 64; }
 
 static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const dirac_st_opts *o) {
   BatchLayout L;
@@ -380,6 +386,18 @@ static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const di
                      : o->pc == DIRAC_ST_PC_LINE   ? take(line_layout(&A[i]->prob, o->precision).total)
                                                    : 0);
   }
+  L.cap_rows = 0;
+  L.cap_vec = 0;
+  L.cap_lines = 0;
+  for (int i = 0; i < nsys; i++) {
+    L.cap_rows += (A[i]->nrows + rows_per_wg_min(A[i]->nc) - 1) / rows_per_wg_min(A[i]->nc);
+    L.cap_vec += L.nblk[i];
+    if (o->pc == DIRAC_ST_PC_LINE) L.cap_lines += (line_layout(&A[i]->prob, o->precision).lines + 63) / 64;
+  }
+  L.tab_w = take(L.cap_rows * 2);
+  L.tab_r = take(L.cap_rows * 2);
+  L.tab_v = take(L.cap_vec * 2);
+  L.tab_l = take(L.cap_lines * 2 + 2);
   L.desc = take(sizeof(BSys) * nsys);
   L.jobs = take(sizeof(LineJob) * nsys);
   L.sjobs = take(sizeof(LineSetupJob) * nsys);
@@ -395,6 +413,9 @@ static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const di
 struct Lists {
   int64_t *dev = nullptr;
   int cap = 0;
+  // workgroup tables and their capacities (entries)
+  uint16_t *tab_w = nullptr, *tab_r = nullptr, *tab_v = nullptr, *tab_l = nullptr;
+  int64_t cap_rows = 0, cap_vec = 0, cap_lines = 0;
   std::vector<int> cur;
   int G = -1, Gres = -1;
   WorkList w{}, r{}, v{}, ph[4]{};
@@ -427,17 +448,27 @@ struct Lists {
     bool fits = hw[na] < (int64_t(1) << 31) && hr[na] < (int64_t(1) << 31) && hv[na] < (int64_t(1) << 31);
     for (int k = 0; k < 4; k++) fits = fits && hp[k * c1 + na] < (int64_t(1) << 31);
     DST_CHECK(fits, "batch too large for one grid");
+    // the workgroup tables are sized for the largest lane count
+    DST_CHECK(hw[na] <= cap_rows && hr[na] <= cap_rows && hv[na] <= cap_vec && hp[3 * c1 + na] <= cap_lines,
+              "internal: work list exceeds its table");
     nw = (unsigned)hw[na];
     nr = (unsigned)hr[na];
     nv = (unsigned)hv[na];
-    w = {dev, dev + c1, na};
-    r = {dev, dev + 2 * c1, na};
-    v = {dev, dev + 3 * c1, na};
+    w = {dev, dev + c1, tab_w, na};
+    r = {dev, dev + 2 * c1, tab_r, na};
+    v = {dev, dev + 3 * c1, tab_v, na};
     for (int k = 0; k < 4; k++) {
       nph[k] = (unsigned)hp[k * c1 + na];
-      ph[k] = {dev, dev + (4 + k) * c1, na};
+      ph[k] = {dev, dev + (4 + k) * c1, k == 3 ? tab_l : nullptr, na};
     }
     DST_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (na > 0) {
+      g_fill_tab<<<na, 256, 0, s>>>(w.off, tab_w);
+      g_fill_tab<<<na, 256, 0, s>>>(r.off, tab_r);
+      g_fill_tab<<<na, 256, 0, s>>>(v.off, tab_v);
+      if (cap_lines > 0) g_fill_tab<<<na, 256, 0, s>>>(ph[3].off, tab_l);
+      DST_LAUNCHED();
+    }
     // the host staging vector is rewritten by the next call: wait for the copy
     DST_HIP(hipStreamSynchronize(s));
     return 0;
@@ -582,6 +613,13 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
   Lists lists;
   lists.dev = (int64_t *)(work + BL.lists);
   lists.cap = nsys;
+  lists.tab_w = (uint16_t *)(work + BL.tab_w);
+  lists.tab_r = (uint16_t *)(work + BL.tab_r);
+  lists.tab_v = (uint16_t *)(work + BL.tab_v);
+  lists.tab_l = (uint16_t *)(work + BL.tab_l);
+  lists.cap_rows = BL.cap_rows;
+  lists.cap_vec = BL.cap_vec;
+  lists.cap_lines = BL.cap_lines;
   for (int i = 0; i < nsys; i++) {
     BSys &q = hs[i];
     fill_desc(q, A[i]);
@@ -930,13 +968,38 @@ extern "C" int dirac_st_fgmres_batched(int32_t nsys, const dirac_st_bsr *const *
   return batched_impl<float>(nsys, A, b, x, opts, (unsigned char *)work, stats, s);
 }
 
-extern "C" size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys) {
-  clear_error();
-  if (nsys < 1 || nsys > kMaxBatch) {
-    set_error("batch size must be in 1..%d", kMaxBatch);
-    return 0;
+// Workspace of dirac_st_spmv_batched: descriptors, list arrays, workgroup
+// tables (sized for the largest lane count).
+struct SpmvBatchLayout {
+  size_t desc, lists, tab_w, tab_r, tab_v, total;
+  int64_t cap_rows, cap_vec;
+};
+
+static SpmvBatchLayout spmv_batch_layout(int32_t nsys, const dirac_st_bsr *const *A) {
+  SpmvBatchLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t r = off;
+    off += align256(b);
+    return r;
+  };
+  for (int i = 0; i < nsys; i++) {
+    L.cap_rows += (A[i]->nrows + rows_per_wg_min(A[i]->nc) - 1) / rows_per_wg_min(A[i]->nc);
+    L.cap_vec += (A[i]->nrows * A[i]->nc + 255) / 256;
   }
-  return align256(sizeof(BSys) * nsys) + align256(sizeof(int64_t) * kListArrays * (nsys + 1));
+  L.desc = take(sizeof(BSys) * nsys);
+  L.lists = take(sizeof(int64_t) * kListArrays * (nsys + 1));
+  L.tab_w = take(L.cap_rows * 2);
+  L.tab_r = take(L.cap_rows * 2);
+  L.tab_v = take(L.cap_vec * 2);
+  L.total = off;
+  return L;
+}
+
+extern "C" size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys, const dirac_st_bsr *const *A) {
+  clear_error();
+  if (check_batch(nsys, A)) return 0;
+  return spmv_batch_layout(nsys, A).total;
 }
 
 extern "C" int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A, int32_t prec,
@@ -950,9 +1013,9 @@ extern "C" int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A,
   const std::vector<int> cands = lane_candidates(nc, prec);
   DST_CHECK(std::find(cands.begin(), cands.end(), (int)lanes) != cands.end(),
             "lanes %d not available for %dx%d blocks at precision %d", lanes, nc, nc, prec);
-  const size_t need = dirac_st_spmv_batched_workspace_bytes(nsys);
-  if (work_bytes < need) {
-    set_error("workspace too small: %zu < %zu bytes", work_bytes, need);
+  const SpmvBatchLayout SL = spmv_batch_layout(nsys, A);
+  if (work_bytes < SL.total) {
+    set_error("workspace too small: %zu < %zu bytes", work_bytes, SL.total);
     return DIRAC_ST_ENOSPACE;
   }
   DST_CHECK(((uintptr_t)work & 255) == 0, "workspace must be 256-byte aligned");
@@ -966,10 +1029,16 @@ extern "C" int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A,
     hs[i].V = y[i];
     hs[i].ldv = 0;
   }
-  BSys *dS = (BSys *)work;
+  unsigned char *wb = (unsigned char *)work;
+  BSys *dS = (BSys *)(wb + SL.desc);
   Lists lists;
-  lists.dev = (int64_t *)((unsigned char *)work + align256(sizeof(BSys) * nsys));
+  lists.dev = (int64_t *)(wb + SL.lists);
   lists.cap = nsys;
+  lists.tab_w = (uint16_t *)(wb + SL.tab_w);
+  lists.tab_r = (uint16_t *)(wb + SL.tab_r);
+  lists.tab_v = (uint16_t *)(wb + SL.tab_v);
+  lists.cap_rows = SL.cap_rows;
+  lists.cap_vec = SL.cap_vec;
   DST_HIP(hipMemcpyAsync(dS, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
   std::vector<int> all(nsys);
   for (int i = 0; i < nsys; i++) all[i] = i;

@@ -85,7 +85,7 @@ _lib.dirac_st_batched_workspace_bytes.argtypes = [_i32, C.POINTER(_BSRP), C.POIN
 _lib.dirac_st_batched_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_fgmres_batched.argtypes = [_i32, C.POINTER(_BSRP), C.POINTER(_vp), C.POINTER(_vp),
                                          C.POINTER(Opts), _vp, C.c_size_t, C.POINTER(Stats), _vp]
-_lib.dirac_st_spmv_batched_workspace_bytes.argtypes = [_i32]
+_lib.dirac_st_spmv_batched_workspace_bytes.argtypes = [_i32, C.POINTER(_BSRP)]
 _lib.dirac_st_spmv_batched_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_spmv_batched.argtypes = [_i32, C.POINTER(_BSRP), _i32, C.POINTER(_vp), C.POINTER(_vp), _i32,
                                        _vp, C.c_size_t, _vp]
@@ -410,6 +410,13 @@ def fgmres_batched(ops, bs, xs=None, opts: Opts | None = None, work=None, allow_
     return xs, infos, rc
 
 
+def spmv_batched_workspace_bytes(ops) -> int:
+    n = int(_lib.dirac_st_spmv_batched_workspace_bytes(len(ops), _bsr_array(ops)))
+    if n == 0:
+        raise DiracError(EINVAL, last_error())
+    return n
+
+
 def spmv_batched(ops, xs, ys=None, lanes=None, work=None):
     """dirac_st_spmv_batched: y_i = A_i x_i for every system in one launch."""
     prec = 64 if xs[0].dtype == torch.complex128 else 32
@@ -417,11 +424,12 @@ def spmv_batched(ops, xs, ys=None, lanes=None, work=None):
         ys = [torch.empty_like(x) for x in xs]
     if lanes is None:
         lanes = (32 if prec == 64 else 16) if ops[0].nc == 2 else 64
-    nbytes = int(_lib.dirac_st_spmv_batched_workspace_bytes(len(ops)))
+    A = _bsr_array(ops)
+    nbytes = int(_lib.dirac_st_spmv_batched_workspace_bytes(len(ops), A))
     if nbytes == 0:
         raise DiracError(EINVAL, last_error())
     work = _work(nbytes, work)
-    _check(_lib.dirac_st_spmv_batched(len(ops), _bsr_array(ops), prec, _ptr_array(xs), _ptr_array(ys),
+    _check(_lib.dirac_st_spmv_batched(len(ops), A, prec, _ptr_array(xs), _ptr_array(ys),
                                       lanes, _ptr(work), work.numel(), _stream()))
     return ys
 
