@@ -318,8 +318,8 @@ def main():
     o32 = D.make_opts(restart=m, max_it=2000, pc="spectral", precision=32, rtol=rtol,
                       inner_rtol=1e-4, vbar=0.0)
     o64 = D.make_opts(restart=m, max_it=2000, pc="spectral", precision=64, rtol=rtol, vbar=0.0)
-    work = torch.empty(max(D.workspace_bytes(op, o32), D.workspace_bytes(op, o64)), dtype=torch.uint8,
-                       device="cuda")
+    work = torch.empty(max(D.workspace_bytes(op, o32, flexible=True), D.workspace_bytes(op, o64, flexible=True)),
+                       dtype=torch.uint8, device="cuda")
 
     def step():
         D.assemble_into(op, psi0, b)

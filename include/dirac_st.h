@@ -259,7 +259,10 @@ size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *opts
  * b: [nrows][nc] complex128.  x: [nrows][nc] complex128, initial guess on
  * entry, solution on exit.  stats: host, may be NULL.  Returns DIRAC_ST_OK,
  * DIRAC_ST_NOT_CONVERGED (max_it or max_cycles reached), or an error
- * (DIRAC_ST_EBREAKDOWN if NaN/Inf appears, e.g. from b). */
+ * (DIRAC_ST_EBREAKDOWN if NaN/Inf appears, e.g. from b).  work_bytes: at least
+ * dirac_st_workspace_bytes(A, opts, 0); with dirac_st_workspace_bytes(A, opts, 1)
+ * or more (and a preconditioner) the preconditioned vectors are kept and the
+ * end-of-cycle update x += Z y needs no second preconditioner application. */
 int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_opts *opts,
                    void *work, size_t work_bytes, dirac_st_stats *stats, void *stream);
 

@@ -702,9 +702,20 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
 
   std::vector<int> all(nsys);
   for (int i = 0; i < nsys; i++) all[i] = i;
-  const int Gres = nc == 2 ? 32 : 64;  // FP64 residual SpMV
+  // FP64 residual SpMV lanes: the complex128 autotuned value once known
+  int Gres = nc == 2 ? 32 : 64;
   int G = 0;
   if (int rc = choose_lanes<T>(hs, dS, lists, all, Gres, G, s)) return rc;
+  if (sizeof(T) == 8) {
+    Gres = G;
+  } else {
+    int64_t rows = 0;
+    for (const BSys &q : hs) rows += q.nrows;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto f = g_tune.find(tune_key(nc, 64, rows));
+    if (g_forced[nc == 4][0]) Gres = g_forced[nc == 4][0];
+    else if (f != g_tune.end()) Gres = f->second;
+  }
 
   for (int i = 0; i < nsys; i++) stats[i].est = 0.0;
   std::vector<double> bnorm(nsys, 0.0), relres(nsys, 1.0), rb(5 * (size_t)nsys);

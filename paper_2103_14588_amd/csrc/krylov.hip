@@ -46,6 +46,11 @@ __global__ __launch_bounds__(256) void norm_pass(const cx<T> *__restrict__ w,
     partial[blockIdx.x] = mk<double2>(red[0] + red[1] + red[2] + red[3], 0.0);
 }
 
+// ctrl->est_abs = ctrl->dots_norm2 (parks a norm^2 so a second one can follow)
+static __global__ void copy_norm_to_est(Ctrl *ctrl) {
+  if (threadIdx.x == 0) ctrl->est_abs = ctrl->dots_norm2;
+}
+
 __global__ __launch_bounds__(256) void zero_c128(double2 *x, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e < n) x[e] = mk<double2>(0, 0);
@@ -203,11 +208,24 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   S.fallback = 0;
   double relres_prev = -1.0;
 
-  // a zero initial guess needs no first SpMV: its residual is b
+  // a zero initial guess needs no first SpMV: its residual is b.  ||x||^2 and
+  // ||b||^2 come back in one read (the norm^2 slot and the estimate slot)
   double xnorm = 0.0, bnorm = 0.0;
-  if (int rc = read_norm(x, xnorm)) return rc;
+  {
+    norm_pass<double><<<nblocks(N), 256, 0, s>>>(x, partial, N);
+    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
+    copy_norm_to_est<<<1, 64, 0, s>>>(ctrl);
+    norm_pass<double><<<nblocks(N), 256, 0, s>>>(b, partial, N);
+    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
+    DST_LAUNCHED();
+    double both[2];
+    DST_HIP(hipMemcpyAsync(&both[0], &ctrl->est_abs, sizeof(double), hipMemcpyDeviceToHost, s));
+    DST_HIP(hipMemcpyAsync(&both[1], &ctrl->dots_norm2, sizeof(double), hipMemcpyDeviceToHost, s));
+    DST_HIP(hipStreamSynchronize(s));
+    xnorm = sqrt(both[0]);
+    bnorm = sqrt(both[1]);
+  }
   bool x_zero = xnorm == 0.0;
-  if (int rc = read_norm(b, bnorm)) return rc;
   if (!std::isfinite(bnorm)) {
     set_error("right-hand side contains NaN or Inf");
     return DIRAC_ST_EBREAKDOWN;
@@ -435,11 +453,15 @@ extern "C" int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x,
   }
   DST_CHECK(((uintptr_t)work & 255) == 0, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
+  // With room for the preconditioned vectors, keep them (flexible form): the
+  // end-of-cycle update is then x += Z y, one preconditioner application
+  // fewer per cycle, same iterates.
+  const bool keep_z = opts->pc != DIRAC_ST_PC_NONE && work_bytes >= gmres_layout(A, opts, true).total;
   if (opts->precision == 64)
     return gmres_impl<double>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work,
-                              stats, s, false, nullptr);
+                              stats, s, keep_z, nullptr);
   return gmres_impl<float>(A, (const double2 *)b, (double2 *)x, opts, (unsigned char *)work, stats,
-                           s, false, nullptr);
+                           s, keep_z, nullptr);
 }
 
 extern "C" int dirac_st_fgmres_nn(const dirac_st_bsr *A, const void *b, void *x,

@@ -182,8 +182,22 @@ __device__ __forceinline__ void reduce_coef(int k, const double2 *__restrict__ p
                                    Ctrl *__restrict__ ctrl, int what, int which) {
   __shared__ double sx[4], sy[4];
   double ax = 0.0, ay = 0.0;
-  for (int64_t b = threadIdx.x; b < nblk; b += 256) {
-    double2 v = partial[(int64_t)k * nblk + b];
+  const double2 *p = partial + (int64_t)k * nblk;
+  int64_t b = threadIdx.x;
+  // eight loads in flight per thread; each thread still sums its entries in
+  // index order, so the result does not depend on the unrolling
+  for (; b + 7 * 256 < nblk; b += 8 * 256) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = p[b + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      ax += v[u].x;
+      ay += v[u].y;
+    }
+  }
+  for (; b < nblk; b += 256) {
+    const double2 v = p[b];
     ax += v.x;
     ay += v.y;
   }

@@ -84,23 +84,24 @@ static void spec_geom(const dirac_st_problem *p, double vbar, SpecGeom &G) {
   }
 }
 
-// Twiddles exp(-2 pi i q / n_a) of every spatial axis, FP64 and FP32 copies.
+// Twiddles exp(-2 pi i q / n_a) of every spatial axis, FP64 and FP32 copies,
+// computed on the device (no host staging, no synchronisation).
+static __global__ void twiddle_kernel(SpecGeom G, double2 *__restrict__ tw64, float2 *__restrict__ tw32) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int a = 1; a <= G.d; a++) {
+    if (q >= G.n[a]) continue;
+    double sn, cs;
+    sincospi(2.0 * (double)q / (double)G.n[a], &sn, &cs);
+    tw64[G.tw_off[a] + q] = mk<double2>(cs, -sn);
+    tw32[G.tw_off[a] + q] = mk<float2>((float)cs, (float)-sn);
+  }
+}
+
 static int spec_twiddles(const SpecGeom &G, unsigned char *base, const SpecLayout &L, hipStream_t s) {
-  int64_t tot = 0;
-  for (int a = 1; a <= G.d; a++) tot += G.n[a];
-  double2 h64[3 * 4096];
-  float2 h32[3 * 4096];
-  DST_CHECK(tot <= 3 * 4096, "axis too long for the spectral preconditioner");
-  for (int a = 1; a <= G.d; a++)
-    for (int q = 0; q < G.n[a]; q++) {
-      const double th = 2.0 * M_PI * (double)q / (double)G.n[a];
-      h64[G.tw_off[a] + q] = mk<double2>(cos(th), -sin(th));
-      h32[G.tw_off[a] + q] = mk<float2>((float)cos(th), (float)-sin(th));
-    }
-  DST_HIP(hipMemcpyAsync(base + L.tw64, h64, tot * sizeof(double2), hipMemcpyHostToDevice, s));
-  DST_HIP(hipMemcpyAsync(base + L.tw32, h32, tot * sizeof(float2), hipMemcpyHostToDevice, s));
-  // the host arrays live on this stack frame: wait for the copies
-  DST_HIP(hipStreamSynchronize(s));
+  int nmax = 1;
+  for (int a = 1; a <= G.d; a++) nmax = G.n[a] > nmax ? G.n[a] : nmax;
+  twiddle_kernel<<<(nmax + 255) / 256, 256, 0, s>>>(G, (double2 *)(base + L.tw64), (float2 *)(base + L.tw32));
+  DST_LAUNCHED();
   return 0;
 }
 

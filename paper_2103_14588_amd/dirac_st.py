@@ -259,8 +259,9 @@ def gmres(op: Operator, b: torch.Tensor, x: torch.Tensor | None = None, opts: Op
         opts = make_opts(**kw)
     if x is None:
         x = torch.zeros_like(b)
-    nbytes = workspace_bytes(op, opts)
-    if work is None or work.numel() < nbytes:
+    # room for the preconditioned vectors: one preconditioner application fewer per cycle
+    nbytes = workspace_bytes(op, opts, flexible=True)
+    if work is None or work.numel() < workspace_bytes(op, opts):
         work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
     st = Stats()
     hist = None
