@@ -338,7 +338,13 @@ __global__ __launch_bounds__(BS) void assemble_kernel(AsmParams P, int32_t *__re
                                                        double2 *__restrict__ bj64,
                                                        float2 *__restrict__ bj32,
                                                        int32_t *__restrict__ nsingular) {
-  __shared__ double2 sblk[BS * NC * NC];
+  // staging of the blocks for coalesced stores.  4x4 blocks: entry-major with
+  // one pad slot per entry row, so that the per-thread writes (fixed entry,
+  // consecutive blocks) do not all hit one bank (measured 6 % faster at 3+1D
+  // 32^4); 2x2 blocks: block-major (faster at 2+1D 128^3)
+  constexpr int LS = BS + 1;
+  __shared__ double2 sblk[NC == 4 ? NC * NC * LS : NC * NC * BS];
+  auto slot = [&](int t, int q) { return NC == 4 ? q * LS + t : t * NC * NC + q; };
   const int64_t kb0 = (int64_t)blockIdx.x * BS;
   const int64_t kb = kb0 + threadIdx.x;
   if (kb < P.nnzb) {
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(BS) void assemble_kernel(AsmParams P, int32_t *__re
     double2 blk[NC * NC];
     block_at<NC, DS>(P, kb, r, k, colnode, diag, blk);
 #pragma unroll
-    for (int q = 0; q < NC * NC; q++) sblk[threadIdx.x * NC * NC + q] = blk[q];
+    for (int q = 0; q < NC * NC; q++) sblk[slot(threadIdx.x, q)] = blk[q];
     col_idx[kb] = (int32_t)colnode;
     if (k == 0) row_ptr[r] = (int32_t)kb;
     if (kb == P.nnzb - 1) row_ptr[P.nrows] = (int32_t)P.nnzb;
@@ -375,10 +381,10 @@ __global__ __launch_bounds__(BS) void assemble_kernel(AsmParams P, int32_t *__re
   const int64_t nb = (P.nnzb - kb0) < BS ? (P.nnzb - kb0) : BS;
   const int nent = (int)nb * NC * NC;
   double2 *v64 = val64 + kb0 * NC * NC;
-  for (int e = threadIdx.x; e < nent; e += BS) v64[e] = sblk[e];
+  for (int e = threadIdx.x; e < nent; e += BS) v64[e] = sblk[slot(e / (NC * NC), e % (NC * NC))];
   if (val32) {
     float2 *v32 = val32 + kb0 * NC * NC;
-    for (int e = threadIdx.x; e < nent; e += BS) v32[e] = to32(sblk[e]);
+    for (int e = threadIdx.x; e < nent; e += BS) v32[e] = to32(sblk[slot(e / (NC * NC), e % (NC * NC))]);
   }
 }
 
