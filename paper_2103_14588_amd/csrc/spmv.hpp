@@ -253,6 +253,137 @@ __device__ __forceinline__ void spmv_tile_st(int64_t tile, int64_t nrows, const 
   }
 }
 
+// Row tiles of the LDS-staged kernel: RPW consecutive rows of one line of
+// axis 1 (fixed tau and, for d = 2, fixed i_2).  Tiles per operator:
+inline int64_t st_tiles(const Stencil &g, int rpw) {
+  return (int64_t)g.nt * (g.S / g.n[1]) * ((g.n[1] + rpw - 1) / rpw);
+}
+
+// The structured SpMV with the x operand staged in LDS (2x2 blocks, d <= 2):
+// the workgroup's rows share their time node and transverse coordinate, so
+// all their neighbours lie in (time slices) x (3 transverse lines, d = 2) x
+// (RPW + 2 consecutive nodes of axis 1); that tile is loaded once,
+// cooperatively, while the value loads are in flight, and every block then
+// reads its x chunk from LDS instead of gathering it from L2.  Measured 10 %
+// faster than gathering at 2+1D 128^3 in complex128 (73 % of HBM peak).
+template <typename T, int DS, int G, bool RESID>
+__device__ __forceinline__ void spmv_tile_lds(int64_t tile, const Stencil &g, const cx<T> *__restrict__ val,
+                                              const cx<T> *__restrict__ x, const cx<T> *__restrict__ bvec,
+                                              cx<T> *__restrict__ y, T alpha) {
+  constexpr int NC = 2;
+  using Ch = typename chunk_of<T>::type;
+  constexpr int J = chunk_of<T>::J;
+  constexpr int IB = NC / J;          // chunks per x node and per block row
+  constexpr int CPB = NC * NC / J;    // chunks per block
+  constexpr int BPI = G / CPB;        // blocks per group slice
+  constexpr int RPW = 256 / G;        // rows per workgroup
+  constexpr int IMASK = (NC - 1) * IB;
+  constexpr int P = DS == 1 ? 3 : 9;
+  constexpr int NY = DS == 1 ? 1 : 3;  // transverse lines
+  constexpr int TW = RPW + 2;          // nodes of axis 1 per line
+  constexpr int MAXB = 3 * P;
+  constexpr int UNR = (MAXB + BPI - 1) / BPI;
+  static_assert(G % CPB == 0 && G <= 64, "group must hold whole blocks");
+  __shared__ Ch xs[3 * NY * TW * IB];
+  const int n1 = g.n[1], n2 = DS == 2 ? g.n[2] : 1;
+  const int tpl = (n1 + RPW - 1) / RPW;
+  const int64_t line = tile / tpl;
+  const int x0 = (int)(tile - line * tpl) * RPW;
+  const int tau = (int)(line / n2) + 1;
+  const int yy = (int)(line - (int64_t)(tau - 1) * n2);
+  const int tau0 = tau >= 2 ? tau - 1 : tau;
+  const int ntime = g.nt == 1 ? 1 : ((tau == 1 || tau == g.nt) ? 2 : 3);
+  const int lane = threadIdx.x % G;
+  const int xr = x0 + (int)(threadIdx.x / G);
+  const bool own = xr < n1;
+  const int64_t row = line * n1 + xr;
+  const int i = (lane / IB) % NC, jc = lane % IB, bofs = lane / CPB;
+  // value loads first: their HBM latency overlaps the x staging
+  Ch v[UNR];
+  int nb = 0;
+  if (own) {
+    int64_t rs;
+    st_row<DS>(g, row, rs, nb);
+    const Ch *vbase = reinterpret_cast<const Ch *>(val + rs * NC * NC + i * NC + jc * J);
+#pragma unroll
+    for (int it = 0; it < UNR; it++) {
+      const int b = bofs + it * BPI;
+      if (b < nb) {
+        if constexpr (sizeof(T) == 8) v[it] = __builtin_nontemporal_load(vbase + (int64_t)b * CPB);
+        else v[it] = vbase[(int64_t)b * CPB];
+      }
+    }
+  }
+  // stage x: chunk e = ((kt NY + ly) TW + lx) IB + c
+  for (int e = threadIdx.x; e < ntime * NY * TW * IB; e += 256) {
+    const int c = e % IB, node = e / IB;
+    const int lx = node % TW, ly = (node / TW) % NY, kt = node / (TW * NY);
+    int xg = (x0 - 1 + lx) % n1;  // the tile can be wider than a short axis
+    xg += xg < 0 ? n1 : 0;
+    int yg = DS == 2 ? yy - 1 + ly : 0;
+    if (DS == 2) {
+      yg += yg < 0 ? n2 : 0;
+      yg -= yg >= n2 ? n2 : 0;
+    }
+    const int64_t col = (int64_t)(tau0 + kt - 1) * g.S + (int64_t)yg * n1 + xg;
+    xs[e] = *reinterpret_cast<const Ch *>(x + col * NC + c * J);
+  }
+  __syncthreads();
+  cx<T> acc = mk<cx<T>>(0, 0);
+  if (own) {
+    // LDS slot of each sorted neighbour along axis 1 (inside the tile) and axis 2
+    int lxk[3], lyk[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      int d = nb_coord(xr, n1, k) - (x0 - 1);
+      d += d < 0 ? n1 : 0;
+      d -= d >= n1 ? n1 : 0;
+      lxk[k] = d;
+      int dy = 0;
+      if (DS == 2) {
+        dy = nb_coord(yy, n2, k) - (yy - 1);
+        dy += dy < 0 ? n2 : 0;
+        dy -= dy >= n2 ? n2 : 0;
+      }
+      lyk[k] = dy;
+    }
+#pragma unroll
+    for (int it = 0; it < UNR; it++) {
+      const int b = bofs + it * BPI;
+      if (b < nb) {
+        const int kt = b / P, rem = b - kt * P;
+        const int ky = DS == 2 ? rem / 3 : 0, kx = rem - ky * 3;
+        const int lx = kx == 0 ? lxk[0] : (kx == 1 ? lxk[1] : lxk[2]);
+        const int ly = ky == 0 ? lyk[0] : (ky == 1 ? lyk[1] : lyk[2]);
+        acc = chunk_mac<T>(acc, v[it], xs[((kt * NY + ly) * TW + lx) * IB + jc]);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    if (off & IMASK) continue;
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+  }
+  if (own && lane == i * IB) {
+    const int64_t o = row * NC + i;
+    if (RESID) {
+      cx<T> bb = bvec[o];
+      y[o] = mk<cx<T>>(bb.x - acc.x, bb.y - acc.y);
+    } else {
+      y[o] = mk<cx<T>>(alpha * acc.x, alpha * acc.y);
+    }
+  }
+}
+
+template <typename T, int DS, int G, bool RESID>
+__global__ __launch_bounds__(256) void spmv_lds_kernel(int64_t ntiles, Stencil g, const cx<T> *__restrict__ val,
+                                                       const cx<T> *__restrict__ x,
+                                                       const cx<T> *__restrict__ bvec,
+                                                       cx<T> *__restrict__ y, T alpha) {
+  spmv_tile_lds<T, DS, G, RESID>(xcd_tile(blockIdx.x, ntiles), g, val, x, bvec, y, alpha);
+}
+
 template <typename T, int NC, int DS, int G, bool RESID>
 __global__ __launch_bounds__(256) void spmv_st_kernel(int64_t nrows, int64_t nwg, Stencil g,
                                                       const cx<T> *__restrict__ val,
@@ -309,21 +440,19 @@ inline hipError_t launch_spmv_st(const dirac_st_bsr *A, const void *val, const v
   if (A->nc == 4)
     return launch_spmv<T>(A->nc, A->nrows, A->row_ptr, A->col_idx, val, x, bvec, y, alpha, resid, st);
   const Stencil g = make_stencil(&A->prob);
-  const int64_t nrows = A->nrows;
   auto go = [&](auto kern, int G) {
-    const int64_t rpw = 256 / G;
-    const int64_t nwg = (nrows + rpw - 1) / rpw;
+    const int64_t ntiles = st_tiles(g, 256 / G);
     const int tk = kt_start(resid ? DIRAC_ST_TIMED_RESID64
                                   : (sizeof(T) == 8 ? DIRAC_ST_TIMED_SPMV64 : DIRAC_ST_TIMED_SPMV32), st);
-    kern<<<(unsigned)nwg, 256, 0, st>>>(nrows, nwg, g, (const cx<T> *)val, (const cx<T> *)x,
-                                        (const cx<T> *)bvec, (cx<T> *)y, alpha);
+    kern<<<(unsigned)ntiles, 256, 0, st>>>(ntiles, g, (const cx<T> *)val, (const cx<T> *)x,
+                                           (const cx<T> *)bvec, (cx<T> *)y, alpha);
     kt_stop(tk, st);
     return hipGetLastError();
   };
   constexpr int G2 = sizeof(T) == 8 ? 32 : 16;
   if (g.d == 1)
-    return resid ? go(spmv_st_kernel<T, 2, 1, G2, true>, G2) : go(spmv_st_kernel<T, 2, 1, G2, false>, G2);
-  return resid ? go(spmv_st_kernel<T, 2, 2, G2, true>, G2) : go(spmv_st_kernel<T, 2, 2, G2, false>, G2);
+    return resid ? go(spmv_lds_kernel<T, 1, G2, true>, G2) : go(spmv_lds_kernel<T, 1, G2, false>, G2);
+  return resid ? go(spmv_lds_kernel<T, 2, G2, true>, G2) : go(spmv_lds_kernel<T, 2, G2, false>, G2);
 }
 
 }  // namespace dst
