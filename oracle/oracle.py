@@ -258,6 +258,47 @@ def spectral_solve(p: Problem, vbar: float, v: np.ndarray) -> np.ndarray:
     return out
 
 
+def time_slab_problem(p: Problem, slabs: int) -> Problem:
+    """The problem of one time slab: n_t / slabs time elements of the same
+    length h_t, the same spatial mesh and potential.  Every potential of the
+    method depends on x only (Sec. 4.3), so all slabs share this operator."""
+    nt = p.n[0]
+    if slabs < 1 or nt % slabs:
+        raise ValueError("slabs must divide n_t")
+    L = nt // slabs
+    q = Problem()
+    C.memmove(C.byref(q), C.byref(p), C.sizeof(Problem))
+    q.n[0] = L
+    q.len[0] = p.len[0] * L / nt
+    return q
+
+
+def time_slab_solve(p: Problem, v: np.ndarray, slabs: int) -> np.ndarray:
+    """Time decomposition (the preconditioner direction named in the
+    concluding section: time-additive Schwarz), non-overlapping: the time
+    interval is cut into `slabs` equal slabs and on each one the Galerkin
+    problem of Sec. 2.1 posed on the slab's own interval is solved exactly,
+    z_k = A_slab^{-1} v_k.  Posing it on the slab's interval means: the slab's
+    first row takes the field before the slab as known data (dropped here, as
+    in the preconditioner's zero initial state) and its last row ends like the
+    last row of the whole interval.  Exact solve: the spectral solve for a
+    constant potential, dense LU otherwise (tiny meshes)."""
+    q = time_slab_problem(p, slabs)
+    v = np.ascontiguousarray(v, np.complex128)
+    n = v.size // slabs
+    out = np.empty_like(v)
+    As = None
+    if p.vkind != 0:
+        As = Matrix(q).dense()
+    for k in range(slabs):
+        vk = v[k * n:(k + 1) * n]
+        if As is None:
+            out[k * n:(k + 1) * n] = spectral_solve(q, 0.0, vk)
+        else:
+            out[k * n:(k + 1) * n] = dense_solve(As, vk)
+    return out
+
+
 def dense_solve(Adense: np.ndarray, b: np.ndarray) -> np.ndarray:
     """Dense LU with partial pivoting (own code, in the C oracle)."""
     a = np.array(Adense, np.complex128, order="C")

@@ -480,3 +480,82 @@ def test_plain_gmres_stagnates_with_node_block_jacobi():
     assert not info["converged"] and info["relres"] > 1e-3
     x, info = A.gmres(b, restart=30, max_it=3000, rtol=1e-10, pc="spectral")
     assert info["converged"] and info["iters"] == 1
+
+
+# ------------------------------------------------------ time decomposition
+SLAB_CASES = [
+    (IN.Spec(d=1, n=[8, 5]), 2),
+    (IN.Spec(d=1, n=[6, 4], vkind=1, v0=1.5, x0=0.4), 3),
+    (IN.Spec(d=2, n=[6, 3, 4], vkind=2, v0=2.0, x0=0.5, lw=0.1), 2),
+    (IN.Spec(d=2, n=[4, 4, 3]), 4),
+    (IN.Spec(d=3, n=[4, 3, 3, 3], vkind=1, v0=1.0, x0=0.3), 2),
+]
+
+
+def slab_operator_from_kron(spec, slabs, k):
+    """Slab k of the Kronecker-built global operator: its rows and columns, with
+    the diagonal time block of its last row replaced by the end-of-interval row
+    when the slab is not the last one.  Interior rows hold B0 = (2h/3) X1 on the
+    diagonal and B+ = X0/2 + (h/6) X1 towards the next row (App. A 1D factors);
+    the last row of an interval holds X0/2 + (h/3) X1 = B+ + B0/4."""
+    p = as_problem(spec)
+    vfun = None if spec.vkind == 0 else (lambda x: O.potential(p, x))
+    K, _ = kron_operator(spec, vfun)
+    nt = spec.n[0]
+    S = spec.spatial * spec.nc
+    L = nt // slabs
+    a0, a1 = k * L, (k + 1) * L
+    As = K[a0 * S:a1 * S, a0 * S:a1 * S].copy()
+    if a1 < nt:
+        t = a1 - 1
+        B0 = K[t * S:(t + 1) * S, t * S:(t + 1) * S]
+        Bp = K[t * S:(t + 1) * S, (t + 1) * S:(t + 2) * S]
+        As[(L - 1) * S:, (L - 1) * S:] = Bp + B0 / 4
+    return As
+
+
+@pytest.mark.parametrize("spec,slabs", SLAB_CASES, ids=lambda c: str(c))
+def test_time_slab_operator_is_restriction_with_end_row(spec, slabs):
+    """The slab problem assembled on the slab's own time interval equals the
+    global operator restricted to the slab, closed by the end-of-interval row,
+    for every slab (the potential does not depend on time)."""
+    p = as_problem(spec)
+    Aslab = O.Matrix(O.time_slab_problem(p, slabs)).dense()
+    for k in range(slabs):
+        ref = slab_operator_from_kron(spec, slabs, k)
+        assert np.abs(Aslab - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("spec,slabs", SLAB_CASES, ids=lambda c: str(c))
+def test_time_slab_solve_inverts_each_slab(spec, slabs):
+    """z = M^{-1} v solves every slab's system and nothing couples the slabs
+    (constant potential: spectral branch; otherwise dense LU)."""
+    p = as_problem(spec)
+    rng = np.random.default_rng(5)
+    N = spec.n[0] * spec.spatial * spec.nc
+    v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    z = O.time_slab_solve(p, v, slabs)
+    n = N // slabs
+    for k in range(slabs):
+        Ak = slab_operator_from_kron(spec, slabs, k)
+        r = Ak @ z[k * n:(k + 1) * n] - v[k * n:(k + 1) * n]
+        assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(v[k * n:(k + 1) * n])
+    # slab locality: changing v on slab 1 leaves every other slab of z unchanged
+    v2 = v.copy()
+    v2[n:2 * n] += 1.0
+    z2 = O.time_slab_solve(p, v2, slabs)
+    for k in range(slabs):
+        if k != 1:
+            assert np.array_equal(z2[k * n:(k + 1) * n], z[k * n:(k + 1) * n])
+
+
+def test_time_slab_solve_one_slab_is_the_exact_inverse():
+    spec = IN.Spec(d=2, n=[5, 3, 4], vkind=1, v0=2.0, x0=0.5)
+    p = as_problem(spec)
+    K, _ = kron_operator(spec, lambda x: O.potential(p, x))
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(K.shape[0]) + 1j * rng.standard_normal(K.shape[0])
+    z = O.time_slab_solve(p, v, 1)
+    assert np.linalg.norm(z - np.linalg.solve(K, v)) <= 1e-11 * np.linalg.norm(z)
+    with pytest.raises(ValueError):
+        O.time_slab_problem(p, 2)
