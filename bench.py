@@ -157,6 +157,31 @@ def klein_bench(args):
                       "runs": runs}))
 
 
+def slabs_bench(args):
+    """Time decomposition on the 2+1D 128^3 packet and Klein step: complex128
+    GMRES(50) to 1e-8 with the time-slab preconditioner for 1 (the exact line
+    inverse), 2, 4, 8 and 32 slabs; iterations, residual and wall time."""
+    import torch
+    from paper_2103_14588_amd import dirac_st as D
+    from paper_2103_14588_amd import inputs as IN
+
+    torch.cuda.set_device(0)
+    cap = args.max_it
+    runs = []
+    for name, wl in (("packet", IN.packet_2p1(128, seed=0)), ("klein", IN.klein_step_2p1(128, v0=2.5, seed=0))):
+        op, b = D.assemble(wl.spec, torch.from_numpy(wl.psi0).cuda())
+        for slabs in (1, 2, 4, 8, 32):
+            D.gmres(op, b, restart=50, max_it=2, rtol=1e-8, pc="slabs", slabs=slabs)
+            _, info = D.gmres(op, b, restart=50, max_it=cap, rtol=1e-8, pc="slabs", slabs=slabs)
+            r = {"workload": name, "slabs": slabs, "iters": info["iters"], "converged": info["converged"],
+                 "relres": info["relres"], "ms": round(info["ms"], 2),
+                 "ms_per_iter": round(info["ms"] / max(info["iters"], 1), 3)}
+            print(r, file=sys.stderr, flush=True)
+            runs.append(r)
+    print(json.dumps({"workload": "2+1D 128^3 packet and Klein step (V0=2.5), complex128 GMRES(50) to 1e-8 with "
+                                  "the time-slab preconditioner, cap %d" % cap, "runs": runs}))
+
+
 def batch_bench(args):
     """64 Klein-step systems on uneven meshes n^3, n ~ U{32..96}, V0 ~ U[0, 3m]
     (seeded): one step = assembly of all 64 operators and right-hand sides,
@@ -273,21 +298,25 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--only", choices=["spmv64", "spmv32", "assemble", "copy"], default=None,
                     help="launch only this kernel --kernel-reps times (for counter runs)")
-    ap.add_argument("--workload", choices=["packet", "packet3", "plane1", "klein", "batch"], default="packet",
+    ap.add_argument("--workload", choices=["packet", "packet3", "plane1", "klein", "batch", "slabs"],
+                    default="packet",
                     help="packet: the 2+1D 128^3 packet step (default bench line); packet3: the 3+1D "
                          "32^4 packet; plane1: the 1+1D 64x64 plane wave; klein: the "
                          "learned-preconditioner comparison on the 128^3 Klein step; batch: 64 "
-                         "uneven Klein-step systems in one batched solve")
+                         "uneven Klein-step systems in one batched solve; slabs: the time-slab "
+                         "preconditioner for 1-32 slabs on the 128^3 packet and Klein step")
     ap.add_argument("--max-it", type=int, default=1500)
     args = ap.parse_args()
-    if args.workload == "klein":
-        return klein_bench(args)
-    if args.workload == "batch":
-        return batch_bench(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); "
               "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "klein":
+        return klein_bench(args)
+    if args.workload == "batch":
+        return batch_bench(args)
+    if args.workload == "slabs":
+        return slabs_bench(args)
 
     import numpy as np
     import torch

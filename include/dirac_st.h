@@ -68,12 +68,22 @@ enum {
   DIRAC_ST_PC_BLOCK_JACOBI = 1, /* inverse of each node's nc x nc diagonal block */
   DIRAC_ST_PC_SPECTRAL = 2,     /* exact inverse of the operator with V replaced by
                                    the constant opts.vbar (periodic uniform mesh) */
-  DIRAC_ST_PC_LINE = 3          /* exact inverse of the operator itself for every
+  DIRAC_ST_PC_LINE = 3,         /* exact inverse of the operator itself for every
                                    potential of the method (all depend on x_1 only):
                                    time eigenbasis, DFT over x_2, x_3, periodic
                                    block-tridiagonal solves along x_1; needs
                                    n_t <= 2048 and workspace for nc*nc*4 factors
                                    per node */
+  DIRAC_ST_PC_TIME_SLABS = 4    /* time decomposition (the direction the paper's
+                                   conclusion proposes, time-additive Schwarz),
+                                   non-overlapping: opts.time_slabs equal slabs
+                                   of time rows; on each slab the exact inverse
+                                   of the same Galerkin problem posed on the
+                                   slab's own time interval (first row: the
+                                   field before the slab is taken as zero; last
+                                   row: ends like the last row of [0, T]),
+                                   solved like DIRAC_ST_PC_LINE.  time_slabs
+                                   must divide n_t; 1 slab = DIRAC_ST_PC_LINE */
 };
 
 /* Problem: the spacetime box [0, len[0]] x [0, len[1]] x ... with n[0] time
@@ -134,6 +144,8 @@ typedef struct {
                          residual falls below inner_rtol times its starting
                          residual (0 = run the full cycle) */
   double vbar;        /* constant potential of DIRAC_ST_PC_SPECTRAL */
+  int32_t time_slabs; /* DIRAC_ST_PC_TIME_SLABS: number of time slabs (>= 1,
+                         divides n_t); ignored by the other preconditioners */
 } dirac_st_opts;
 
 typedef struct {
@@ -238,13 +250,14 @@ int dirac_st_assemble(const dirac_st_problem *prob, const void *psi0, dirac_st_b
  * row_ptr / col_idx are not read; 4x4 blocks use them. */
 int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x, void *y, void *stream);
 
-/* z = M^{-1} v for the preconditioner `pc` (DIRAC_ST_PC_*) in precision prec
- * (64: complex128, 32: complex64).  work: workspace of at least
- * dirac_st_workspace_bytes(A, opts, 0) bytes for opts->pc = pc (the spectral
- * and line preconditioners keep their factorisations there; the call sets them
- * up and, for the line preconditioner, synchronises the stream). */
-int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec, double vbar, const void *v,
-                      void *z, void *work, size_t work_bytes, void *stream);
+/* z = M^{-1} v for the preconditioner opts->pc (DIRAC_ST_PC_*, not NONE) in
+ * precision opts->precision (64: complex128, 32: complex64), with its
+ * parameters opts->vbar / opts->time_slabs.  work: workspace of at least
+ * dirac_st_workspace_bytes(A, opts, 0) bytes (the spectral, line and time-slab
+ * preconditioners keep their factorisations there; the call sets them up and,
+ * for the line and time-slab preconditioners, synchronises the stream). */
+int dirac_st_pc_apply(const dirac_st_bsr *A, const dirac_st_opts *opts, const void *v, void *z,
+                      void *work, size_t work_bytes, void *stream);
 
 /* Bytes of device workspace needed by dirac_st_gmres (flexible = 0) or
  * dirac_st_fgmres_nn (flexible = 1) for these options: basis of restart+1

@@ -383,7 +383,7 @@ static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const di
     L.partial.push_back(take((size_t)L.nblk.back() * kMaxRestart * sizeof(double2)));
     L.ctrl.push_back(take(sizeof(Ctrl)));
     L.spec.push_back(o->pc == DIRAC_ST_PC_SPECTRAL ? take(spec_layout(&A[i]->prob, o->precision).total)
-                     : o->pc == DIRAC_ST_PC_LINE   ? take(line_layout(&A[i]->prob, o->precision).total)
+                     : line_kind(o->pc) ? take(line_layout(&A[i]->prob, o->precision, pc_slabs(o)).total)
                                                    : 0);
   }
   L.cap_rows = 0;
@@ -392,7 +392,7 @@ static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const di
   for (int i = 0; i < nsys; i++) {
     L.cap_rows += (A[i]->nrows + rows_per_wg_min(A[i]->nc) - 1) / rows_per_wg_min(A[i]->nc);
     L.cap_vec += L.nblk[i];
-    if (o->pc == DIRAC_ST_PC_LINE) L.cap_lines += (line_layout(&A[i]->prob, o->precision).lines + 63) / 64;
+    if (line_kind(o->pc)) L.cap_lines += (line_layout(&A[i]->prob, o->precision, pc_slabs(o)).lines + 63) / 64;
   }
   L.tab_w = take(L.cap_rows * 2);
   L.tab_r = take(L.cap_rows * 2);
@@ -607,8 +607,9 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
   LineJob *dJ = (LineJob *)(work + BL.jobs);
   LineSetupJob *dSJ = (LineSetupJob *)(work + BL.sjobs);
   std::vector<LineJob> jobs(nsys);
-  std::vector<LineSetupJob> sjobs(o->pc == DIRAC_ST_PC_LINE ? nsys : 0);
-  std::vector<LineStaging> staging(o->pc == DIRAC_ST_PC_LINE ? nsys : 0);
+  const bool linepc = line_kind(o->pc);
+  std::vector<LineSetupJob> sjobs(linepc ? nsys : 0);
+  std::vector<LineStaging> staging(linepc ? nsys : 0);
   double *dGat = (double *)(work + BL.gather);
   Lists lists;
   lists.dev = (int64_t *)(work + BL.lists);
@@ -631,18 +632,19 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
     q.b = (const double2 *)b[i];
     q.partial = (double2 *)(work + BL.partial[i]);
     q.ctrl = (Ctrl *)(work + BL.ctrl[i]);
-    if (o->pc == DIRAC_ST_PC_LINE) {
+    if (linepc) {
       // host part now; the factorisations run grouped once every system is prepared
-      pcs[i].kind = DIRAC_ST_PC_LINE;
+      pcs[i].kind = o->pc;
       pcs[i].prec = sizeof(T) == 8 ? 64 : 32;
       pcs[i].A = A[i];
+      pcs[i].slabs = pc_slabs(o);
       if (int rc = line_prepare<T>(pcs[i], A[i], work + BL.spec[i], staging[i], s)) return rc;
     } else if (o->pc != DIRAC_ST_PC_NONE) {
       const double vbar = o->vbar >= 0.0 ? o->vbar : 0.5 * A[i]->prob.v0;
       if (int rc = pc_setup<T>(pcs[i], A[i], o->pc, vbar, work + BL.spec[i], s)) return rc;
     }
     for (int k = 0; k < 4; k++) q.lt[k] = 0;
-    if (o->pc == DIRAC_ST_PC_LINE) {
+    if (linepc) {
       const LineLayout &LL = pcs[i].LL;
       const dirac_st_problem &pr = A[i]->prob;
       unsigned char *lb = pcs[i].line;
@@ -659,12 +661,12 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
       jb.pm = LL.pm;
       jb.d = pr.d;
       jb.nc = pr.nc;
-      jb.nt = pr.n[0];
+      jb.nt = LL.tl;  // rows of one time slab; the time transform runs per slab
       jb.S = q.nrows / pr.n[0];
       jb.lines = LL.lines;
       for (int a = 0; a < 4; a++) jb.n[a] = a <= pr.d ? pr.n[a] : 1;
       const int64_t ncol = jb.S * pr.nc;
-      q.lt[0] = (ncol + 63) / 64 * (LL.pm / 64);
+      q.lt[0] = (int64_t)LL.slabs * ((ncol + 63) / 64) * (LL.pm / 64);
       for (int a = 2; a <= pr.d; a++) {
         jb.F[a] = lb + (dbl ? LL.f64[a] : LL.f32[a]);
         jb.Fi[a] = lb + (dbl ? LL.fi64[a] : LL.fi32[a]);
@@ -687,7 +689,7 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
       sj.flag = (int *)(lb + LL.flag);
     }
   }
-  if (o->pc == DIRAC_ST_PC_LINE) {
+  if (linepc) {
     DST_HIP(hipMemcpyAsync(dJ, jobs.data(), sizeof(LineJob) * nsys, hipMemcpyHostToDevice, s));
     DST_HIP(hipMemcpyAsync(dSJ, sjobs.data(), sizeof(LineSetupJob) * nsys, hipMemcpyHostToDevice, s));
   }
@@ -740,7 +742,7 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
   };
 
   if (int rc = lists.set(hs, all, G, Gres, s)) return rc;
-  if (o->pc == DIRAC_ST_PC_LINE) {
+  if (linepc) {
     const int d = A[0]->prob.d;
     if (d == 1) g_line_setup<T, 2, 1><<<lists.nph[3], 64, 0, s>>>(dSJ, lists.ph[3]);
     else if (d == 2) g_line_setup<T, 2, 2><<<lists.nph[3], 64, 0, s>>>(dSJ, lists.ph[3]);
@@ -819,7 +821,7 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
       if (int rc = lists.set(hs, step, G, Gres, s)) return rc;
       const unsigned na = (unsigned)step.size();
       // Z_j = M^{-1} (sigma_j V_j)
-      if (o->pc == DIRAC_ST_PC_LINE) {
+      if (linepc) {
         // Q along time, transverse DFTs, line solves, inverse DFTs, sigma_j W
         const int d = A[0]->prob.d;
         const int64_t *act = lists.w.act;
@@ -940,9 +942,9 @@ static int check_batch_opts(int32_t nsys, const dirac_st_bsr *const *A, const di
   DST_CHECK(o, "opts is NULL");
   DST_CHECK(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in 1..%d", kMaxRestart);
   DST_CHECK(o->precision == 64 || o->precision == 32, "precision must be 64 or 32");
-  DST_CHECK(o->pc >= DIRAC_ST_PC_NONE && o->pc <= DIRAC_ST_PC_LINE, "unknown preconditioner %d", o->pc);
   DST_CHECK(o->rtol > 0.0 && o->max_it >= 0, "rtol must be positive and max_it >= 0");
   for (int i = 0; i < nsys; i++) {
+    if (int rc = check_pc_opts(A[i], o)) return rc;
     DST_CHECK(A[i]->prob.d == A[0]->prob.d, "all systems of a batched solve must have the same dimension");
     DST_CHECK(o->precision == 64 || A[i]->val32, "system %d: precision 32 needs val32", i);
     if (o->pc == DIRAC_ST_PC_BLOCK_JACOBI)

@@ -121,7 +121,11 @@ static GmresLayout gmres_layout(const dirac_st_bsr *A, const dirac_st_opts *o, b
   off += align256(sizeof(Ctrl));
   L.spec = off;
   if (o->pc == DIRAC_ST_PC_SPECTRAL) off += spec_layout(&A->prob, o->precision).total;
-  if (o->pc == DIRAC_ST_PC_LINE) off += line_layout(&A->prob, o->precision).total;
+  if (line_kind(o->pc)) {
+    // an invalid slab count is rejected by the solver; size as one slab (the largest)
+    const int sl = pc_slabs(o);
+    off += line_layout(&A->prob, o->precision, sl >= 1 && A->prob.n[0] % sl == 0 ? sl : 1).total;
+  }
   L.Z = off;
   if (flexible) off += vb * (size_t)o->restart;
   L.nn = off;
@@ -179,7 +183,7 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   const void *val = sizeof(T) == 8 ? A->val64 : A->val32;
 
   Precond P;
-  if (int rc = pc_setup<T>(P, A, o->pc, o->vbar, work + L.spec, s)) return rc;
+  if (int rc = pc_setup<T>(P, A, o->pc, o->vbar, work + L.spec, s, pc_slabs(o))) return rc;
   if (net) {
     P.nn = net;
     P.nn_on = true;
@@ -404,20 +408,23 @@ extern "C" size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st
   return gmres_layout(A, &oo, flexible != 0).total;
 }
 
-extern "C" int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec, double vbar,
-                                 const void *v, void *z, void *work, size_t work_bytes,
-                                 void *stream) {
+extern "C" int dirac_st_pc_apply(const dirac_st_bsr *A, const dirac_st_opts *opts, const void *v, void *z,
+                                 void *work, size_t work_bytes, void *stream) {
   clear_error();
   if (int rc = check_bsr(A)) return rc;
-  DST_CHECK(prec == 64 || prec == 32, "prec must be 64 or 32");
-  DST_CHECK(pc >= DIRAC_ST_PC_BLOCK_JACOBI && pc <= DIRAC_ST_PC_LINE, "pc must be 1, 2 or 3");
+  DST_CHECK(opts != nullptr, "opts is NULL");
+  const int pc = opts->pc, prec = opts->precision;
+  DST_CHECK(prec == 64 || prec == 32, "precision must be 64 or 32");
+  DST_CHECK(pc != DIRAC_ST_PC_NONE, "no preconditioner to apply");
+  if (int rc = check_pc_opts(A, opts)) return rc;
   DST_CHECK(v && z && v != z, "v and z must be set and distinct");
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = A->nrows * A->nc;
-  if (pc == DIRAC_ST_PC_SPECTRAL || pc == DIRAC_ST_PC_LINE) {
-    const size_t need =
-        pc == DIRAC_ST_PC_SPECTRAL ? spec_layout(&A->prob, prec).total : line_layout(&A->prob, prec).total;
+  if (pc == DIRAC_ST_PC_SPECTRAL || line_kind(pc)) {
+    const size_t need = pc == DIRAC_ST_PC_SPECTRAL ? spec_layout(&A->prob, prec).total
+                                                   : line_layout(&A->prob, prec, pc_slabs(opts)).total;
     DST_CHECK(work != nullptr, "this preconditioner needs a workspace");
+    DST_CHECK(((uintptr_t)work & 255) == 0, "workspace must be 256-byte aligned");
     if (work_bytes < need) {
       set_error("workspace too small: %zu < %zu", work_bytes, need);
       return DIRAC_ST_ENOSPACE;
@@ -425,10 +432,10 @@ extern "C" int dirac_st_pc_apply(const dirac_st_bsr *A, int32_t pc, int32_t prec
   }
   Precond P;
   if (prec == 64) {
-    if (int rc = pc_setup<double>(P, A, pc, vbar, (unsigned char *)work, s)) return rc;
+    if (int rc = pc_setup<double>(P, A, pc, opts->vbar, (unsigned char *)work, s, pc_slabs(opts))) return rc;
     return pc_apply<double>(P, (const double2 *)v, (double2 *)z, 1.0, N, s);
   }
-  if (int rc = pc_setup<float>(P, A, pc, vbar, (unsigned char *)work, s)) return rc;
+  if (int rc = pc_setup<float>(P, A, pc, opts->vbar, (unsigned char *)work, s, pc_slabs(opts))) return rc;
   return pc_apply<float>(P, (const float2 *)v, (float2 *)z, 1.0, N, s);
 }
 
@@ -443,7 +450,7 @@ extern "C" int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x,
             kMaxRestart);
   DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
   DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
-  DST_CHECK(opts->pc >= DIRAC_ST_PC_NONE && opts->pc <= DIRAC_ST_PC_LINE, "unknown preconditioner %d", opts->pc);
+  if (int rc = check_pc_opts(A, opts)) return rc;
   DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
   DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
   const size_t need = gmres_layout(A, opts, false).total;
@@ -475,7 +482,7 @@ extern "C" int dirac_st_fgmres_nn(const dirac_st_bsr *A, const void *b, void *x,
             kMaxRestart);
   DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
   DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
-  DST_CHECK(opts->pc >= DIRAC_ST_PC_NONE && opts->pc <= DIRAC_ST_PC_LINE, "unknown preconditioner %d", opts->pc);
+  if (int rc = check_pc_opts(A, opts)) return rc;
   DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
   DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
   DST_CHECK(!net || A->prob.d == 2, "the network preconditioner is for 2+1D operators");

@@ -42,19 +42,24 @@ struct LineLayout {
   int dpm[4], dpk[4];
   int pm, pk;      // Q and W padded to pm x pk (multiples of 64 and 16), zero filled
   int64_t lines;   // n_t * (spatial nodes / n_1)
+  int slabs, tl;   // time slabs and rows per slab (tl x tl time factors)
 };
 
-inline LineLayout line_layout(const dirac_st_problem *p, int prec) {
+// slabs = 1: the whole time interval; slabs > 1: the time-slab decomposition,
+// every slab the same tl = n_t / slabs rows (the caller checks divisibility)
+inline LineLayout line_layout(const dirac_st_problem *p, int prec, int slabs = 1) {
   LineLayout L{};
   const int nt = p->n[0], nc = p->nc;
+  L.slabs = slabs;
+  L.tl = nt / slabs;
   int64_t S = 1, twn = 0;
   for (int a = 1; a <= p->d; a++) {
     S *= p->n[a];
     twn += p->n[a];
   }
   L.lines = (int64_t)nt * (S / p->n[1]);
-  L.pm = (nt + 63) / 64 * 64;
-  L.pk = (nt + 15) / 16 * 16;
+  L.pm = (L.tl + 63) / 64 * 64;
+  L.pk = (L.tl + 15) / 16 * 16;
   const size_t cs = prec == 64 ? 16 : 8;
   size_t off = 0;
   auto take = [&](size_t b) {

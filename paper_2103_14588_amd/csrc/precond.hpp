@@ -22,6 +22,19 @@ namespace dst {
 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// the line and time-slab preconditioners share their set-up and apply
+static inline bool line_kind(int pc) { return pc == DIRAC_ST_PC_LINE || pc == DIRAC_ST_PC_TIME_SLABS; }
+static inline int pc_slabs(const dirac_st_opts *o) { return o->pc == DIRAC_ST_PC_TIME_SLABS ? o->time_slabs : 1; }
+
+// preconditioner parameters that the problem must admit
+static inline int check_pc_opts(const dirac_st_bsr *A, const dirac_st_opts *o) {
+  DST_CHECK(o->pc >= DIRAC_ST_PC_NONE && o->pc <= DIRAC_ST_PC_TIME_SLABS, "unknown preconditioner %d", o->pc);
+  if (o->pc == DIRAC_ST_PC_TIME_SLABS)
+    DST_CHECK(o->time_slabs >= 1 && A->prob.n[0] % o->time_slabs == 0,
+              "time_slabs must be >= 1 and divide n_t = %d (got %d)", A->prob.n[0], o->time_slabs);
+  return 0;
+}
+
 // ------------------------------------------------------------ preconditioner
 struct Precond {
   int kind = DIRAC_ST_PC_NONE;
@@ -34,6 +47,7 @@ struct Precond {
   // line (shares G and the twiddle tables' geometry)
   unsigned char *line = nullptr;
   LineLayout LL{};
+  int slabs = 1;  // time slabs of DIRAC_ST_PC_TIME_SLABS (1 for the line preconditioner)
   // learned correction z += s N(v / s) (flexible GMRES only)
   const dirac_st_nn *nn = nullptr;
   bool nn_on = false;
@@ -130,9 +144,10 @@ template <typename T>
 static int line_prepare(Precond &P, const dirac_st_bsr *A, unsigned char *base, LineStaging &st,
                         hipStream_t s) {
   const dirac_st_problem *p = &A->prob;
-  DST_CHECK(p->n[0] <= kTimeEigenMax, "line preconditioner needs n_t <= %d", kTimeEigenMax);
+  DST_CHECK(P.slabs >= 1 && p->n[0] % P.slabs == 0, "time slabs must divide n_t");
+  DST_CHECK(p->n[0] / P.slabs <= kTimeEigenMax, "line preconditioner needs n_t per slab <= %d", kTimeEigenMax);
   P.line = base;
-  P.LL = line_layout(p, P.prec);
+  P.LL = line_layout(p, P.prec, P.slabs);
   const LineLayout &L = P.LL;
   spec_geom(p, 0.0, P.G);
   int64_t twn = 0;
@@ -145,19 +160,21 @@ static int line_prepare(Precond &P, const dirac_st_bsr *A, unsigned char *base, 
       st.tw64[P.G.tw_off[a] + q] = mk<double2>(cos(th), -sin(th));
       st.tw32[P.G.tw_off[a] + q] = mk<float2>((float)cos(th), (float)-sin(th));
     }
-  const int nt = p->n[0], n1 = p->n[1];
+  // every slab has the pencil of a whole interval of tl rows (first row
+  // interior-like, last row the end row), so one decomposition serves all
+  const int nt = p->n[0], n1 = p->n[1], tl = L.tl;
   std::vector<std::complex<double>> lam, W, Q;
-  if (int rc = time_eigen(nt, p->len[0] / nt, lam, W, Q)) return rc;
+  if (int rc = time_eigen(tl, p->len[0] / nt, lam, W, Q)) return rc;
   st.q64.assign((size_t)L.pm * L.pk, mk<double2>(0, 0));
   st.w64.assign(st.q64.size(), mk<double2>(0, 0));
   st.q32.assign(st.q64.size(), mk<float2>(0, 0));
   st.w32.assign(st.q64.size(), mk<float2>(0, 0));
-  st.l64.resize(nt);
-  for (int r = 0; r < nt; r++) {
-    st.l64[r] = mk<double2>(lam[r].real(), lam[r].imag());
-    for (int c = 0; c < nt; c++) {
+  st.l64.resize(nt);  // eigenvalue of time row r: that of its row in the slab
+  for (int r = 0; r < nt; r++) st.l64[r] = mk<double2>(lam[r % tl].real(), lam[r % tl].imag());
+  for (int r = 0; r < tl; r++) {
+    for (int c = 0; c < tl; c++) {
       const size_t e = (size_t)r * L.pk + c;
-      const std::complex<double> qv = Q[(size_t)r * nt + c], wv = W[(size_t)r * nt + c];
+      const std::complex<double> qv = Q[(size_t)r * tl + c], wv = W[(size_t)r * tl + c];
       st.q64[e] = mk<double2>(qv.real(), qv.imag());
       st.w64[e] = mk<double2>(wv.real(), wv.imag());
       st.q32[e] = mk<float2>((float)qv.real(), (float)qv.imag());
@@ -282,15 +299,16 @@ static int axis_transform(const SpecGeom &G, const cx<T> *tw, const cx<T> *in, c
 
 template <typename T>
 static int pc_setup(Precond &P, const dirac_st_bsr *A, int kind, double vbar, unsigned char *spec,
-                    hipStream_t s) {
+                    hipStream_t s, int slabs = 1) {
   P.kind = kind;
+  P.slabs = kind == DIRAC_ST_PC_TIME_SLABS ? slabs : 1;
   P.prec = sizeof(T) == 8 ? 64 : 32;
   P.A = A;
   if (kind == DIRAC_ST_PC_BLOCK_JACOBI) {
     DST_CHECK((sizeof(T) == 8 ? A->bjinv64 : A->bjinv32) != nullptr,
               "block-Jacobi preconditioner needs bjinv%d", P.prec);
   }
-  if (kind == DIRAC_ST_PC_LINE) return line_setup_host<T>(P, A, spec, s);
+  if (line_kind(kind)) return line_setup_host<T>(P, A, spec, s);
   if (kind != DIRAC_ST_PC_SPECTRAL) return 0;
   P.spec = spec;
   P.SL = spec_layout(&A->prob, P.prec);
@@ -353,7 +371,7 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
     }
     return 0;
   }
-  if (P.kind == DIRAC_ST_PC_LINE) {
+  if (line_kind(P.kind)) {
     const SpecGeom &G = P.G;
     const LineLayout &L = P.LL;
     const bool dbl = sizeof(T) == 8;
@@ -361,9 +379,9 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
     const cx<T> *Wm = (const cx<T> *)(P.line + (dbl ? L.w64 : L.w32));
     cx<T> *b1 = (cx<T> *)(P.line + L.buf), *b2 = (cx<T> *)(P.line + L.buf2);
     const int64_t ncol = G.S * G.nc;
-    // b1 = Q v along time
-    tgemm<T><<<dim3((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64), 1), 256, 0, s>>>(
-        Qm, L.pk, v, b1, G.nt, ncol, (T)1);
+    // b1 = Q v along time, per slab
+    tgemm<T><<<dim3((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64), (unsigned)L.slabs), 256, 0, s>>>(
+        Qm, L.pk, v, b1, L.tl, ncol, (T)1);
     DST_LAUNCHED();
     // transverse DFTs, slowest axis first, ping-pong b1 <-> b2
     auto transverse = [&](int a, bool inverse, const cx<T> *in, cx<T> *out) -> int {
@@ -397,9 +415,9 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
       if (int rc = transverse(a, true, cur, oth)) return rc;
       std::swap(cur, oth);
     }
-    // z = scale * W cur along time
-    tgemm<T><<<dim3((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64), 1), 256, 0, s>>>(
-        Wm, L.pk, cur, z, G.nt, ncol, (T)scale);
+    // z = scale * W cur along time, per slab
+    tgemm<T><<<dim3((unsigned)((ncol + 63) / 64), (unsigned)(L.pm / 64), (unsigned)L.slabs), 256, 0, s>>>(
+        Wm, L.pk, cur, z, L.tl, ncol, (T)scale);
     DST_LAUNCHED();
     return 0;
   }

@@ -21,8 +21,9 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, NOT_CONVERGED, EINVAL, EHIP, EBREAKDOWN, ENOSPACE = 0, 1, -1, -2, -3, -4
 V_NONE, V_STEP, V_SMOOTH = 0, 1, 2
-PC_NONE, PC_BLOCK_JACOBI, PC_SPECTRAL, PC_LINE = 0, 1, 2, 3
-PC_NAMES = {"none": PC_NONE, "bj": PC_BLOCK_JACOBI, "spectral": PC_SPECTRAL, "line": PC_LINE}
+PC_NONE, PC_BLOCK_JACOBI, PC_SPECTRAL, PC_LINE, PC_TIME_SLABS = 0, 1, 2, 3, 4
+PC_NAMES = {"none": PC_NONE, "bj": PC_BLOCK_JACOBI, "spectral": PC_SPECTRAL, "line": PC_LINE,
+            "slabs": PC_TIME_SLABS}
 
 
 class Problem(C.Structure):
@@ -41,7 +42,7 @@ class BSR(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("pc", C.c_int32),
                 ("precision", C.c_int32), ("max_cycles", C.c_int32), ("rtol", C.c_double),
-                ("inner_rtol", C.c_double), ("vbar", C.c_double)]
+                ("inner_rtol", C.c_double), ("vbar", C.c_double), ("time_slabs", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -61,7 +62,7 @@ _lib.dirac_st_last_error.restype = C.c_char_p
 _lib.dirac_st_sizes.argtypes = [C.POINTER(Problem), C.POINTER(_i64), C.POINTER(_i64)]
 _lib.dirac_st_assemble.argtypes = [C.POINTER(Problem), _vp, C.POINTER(BSR), _vp, _vp]
 _lib.dirac_st_spmv.argtypes = [C.POINTER(BSR), _i32, _vp, _vp, _vp]
-_lib.dirac_st_pc_apply.argtypes = [C.POINTER(BSR), _i32, _i32, C.c_double, _vp, _vp, _vp, C.c_size_t, _vp]
+_lib.dirac_st_pc_apply.argtypes = [C.POINTER(BSR), C.POINTER(Opts), _vp, _vp, _vp, C.c_size_t, _vp]
 _lib.dirac_st_workspace_bytes.argtypes = [C.POINTER(BSR), C.POINTER(Opts), _i32]
 _lib.dirac_st_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_gmres.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, C.c_size_t,
@@ -224,28 +225,27 @@ def spmv(op: Operator, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.
     return y
 
 
-def pc_apply(op: Operator, v: torch.Tensor, pc="spectral", vbar=0.0, z=None, work=None):
+def pc_apply(op: Operator, v: torch.Tensor, pc="spectral", vbar=0.0, z=None, work=None, slabs=1):
     prec = 64 if v.dtype == torch.complex128 else 32
     kind = PC_NAMES[pc] if isinstance(pc, str) else pc
     if z is None:
         z = torch.empty_like(v)
     o = Opts(restart=1, max_it=1, pc=kind, precision=prec, max_cycles=0, rtol=1e-8, inner_rtol=0.0,
-             vbar=vbar)
-    nbytes = 0
-    if kind in (PC_SPECTRAL, PC_LINE):
+             vbar=vbar, time_slabs=slabs)
+    if kind in (PC_SPECTRAL, PC_LINE, PC_TIME_SLABS):
         nbytes = _lib.dirac_st_workspace_bytes(C.byref(op.bsr), C.byref(o), 0)
         if work is None or work.numel() < nbytes:
             work = torch.empty(nbytes, dtype=torch.uint8, device=v.device)
-    _check(_lib.dirac_st_pc_apply(C.byref(op.bsr), kind, prec, vbar, _ptr(v), _ptr(z), _ptr(work),
+    _check(_lib.dirac_st_pc_apply(C.byref(op.bsr), C.byref(o), _ptr(v), _ptr(z), _ptr(work),
                                   work.numel() if work is not None else 0, _stream()))
     return z
 
 
 def make_opts(restart=50, max_it=20000, pc="bj", precision=64, max_cycles=0, rtol=1e-8,
-              inner_rtol=0.0, vbar=0.0) -> Opts:
+              inner_rtol=0.0, vbar=0.0, slabs=1) -> Opts:
     return Opts(restart=restart, max_it=max_it, pc=PC_NAMES[pc] if isinstance(pc, str) else pc,
                 precision=precision, max_cycles=max_cycles, rtol=rtol, inner_rtol=inner_rtol,
-                vbar=vbar)
+                vbar=vbar, time_slabs=slabs)
 
 
 def workspace_bytes(op: Operator, opts: Opts, flexible=False) -> int:
