@@ -805,6 +805,107 @@ done:
   return st->converged ? 0 : (st->breakdown ? -3 : 1);
 }
 
+/* ---------------------------------------------------------------- BiCGSTAB */
+/* BiCGSTAB (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992)), the second
+ * Krylov solver of the paper's parallel runs (Sec. 4.4, Tables 1-3), with right
+ * preconditioning so that r is the residual of the original system:
+ *   r = b - A x, rh = r, rho_old = alpha = omega = 1, p = v = 0
+ *   each iteration:
+ *     rho = rh^H r;  beta = (rho / rho_old) (alpha / omega)
+ *     p = r + beta (p - omega v);  ph = M^{-1} p;  v = A ph
+ *     alpha = rho / (rh^H v);  s = r - alpha v
+ *     sh = M^{-1} s;  t = A sh;  omega = (t^H s) / (t^H t)  (0 if t = 0)
+ *     x += alpha ph + omega sh;  r = s - omega t
+ * The stop test uses the updated residual; when it passes, the true residual
+ * b - A x decides, and if that fails (the two drifted apart) the iteration
+ * restarts from the true residual with rh = r.  A zero rho or rh^H v also
+ * restarts (from the true residual); a restart that is immediately hit again
+ * ends the solve as a breakdown.  hist (may be NULL, length >= max_it)
+ * receives ||r|| / ||b|| after every iteration; st->restarts counts the starts. */
+int orc_bicgstab(const orc_matrix *A, int pc_kind, double vbar, orc_pc_fn fn, void *ctx,
+                 const cplx *b, cplx *x, int max_it, double rtol, orc_stats *st, double *hist) {
+  const int nc = A->p.nc;
+  const int64_t N = A->nrows * nc;
+  pc_state pc = {A, pc_kind, NULL, vbar, fn, ctx};
+  if (pc_kind == 1) {
+    pc.bj = malloc(sizeof(cplx) * A->nrows * nc * nc);
+    orc_block_jacobi(A, pc.bj);
+  }
+  cplx *r = malloc(sizeof(cplx) * N), *rh = malloc(sizeof(cplx) * N), *p = malloc(sizeof(cplx) * N);
+  cplx *v = malloc(sizeof(cplx) * N), *ph = malloc(sizeof(cplx) * N), *s = malloc(sizeof(cplx) * N);
+  cplx *sh = malloc(sizeof(cplx) * N), *t = malloc(sizeof(cplx) * N);
+  memset(st, 0, sizeof(*st));
+  const double bnorm = vnorm(N, b);
+  int its = 0, fresh = 0;
+  cplx rho_old = 1, alpha = 1, omega = 1;
+  if (bnorm == 0.0) {
+    memset(x, 0, sizeof(cplx) * N);
+    st->converged = 1;
+    goto done;
+  }
+  for (;;) {
+    /* (re)start from the true residual */
+    orc_spmv(A, x, r);
+    for (int64_t i = 0; i < N; i++) r[i] = b[i] - r[i];
+    const double rn = vnorm(N, r);
+    st->relres = rn / bnorm;
+    if (!isfinite(rn)) { st->breakdown = 1; break; }
+    if (st->relres <= rtol) { st->converged = 1; break; }
+    if (its >= max_it) break;
+    if (fresh) { st->breakdown = 1; break; }  /* restarted and broke down at once */
+    st->restarts++;
+    fresh = 1;
+    memcpy(rh, r, sizeof(cplx) * N);
+    memset(p, 0, sizeof(cplx) * N);
+    memset(v, 0, sizeof(cplx) * N);
+    rho_old = alpha = omega = 1;
+    int restart = 0;
+    while (its < max_it) {
+      const cplx rho = vdot(N, rh, r);
+      if (rho == 0) { restart = 1; break; }
+      const cplx beta = (rho / rho_old) * (alpha / omega);
+      for (int64_t i = 0; i < N; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      pc_apply(&pc, p, ph, N);
+      orc_spmv(A, ph, v);
+      const cplx rv = vdot(N, rh, v);
+      if (rv == 0) { restart = 1; break; }
+      alpha = rho / rv;
+      for (int64_t i = 0; i < N; i++) s[i] = r[i] - alpha * v[i];
+      pc_apply(&pc, s, sh, N);
+      orc_spmv(A, sh, t);
+      const double tt = creal(vdot(N, t, t));
+      omega = tt > 0.0 ? vdot(N, t, s) / tt : 0.0;
+      for (int64_t i = 0; i < N; i++) {
+        x[i] += alpha * ph[i] + omega * sh[i];
+        r[i] = s[i] - omega * t[i];
+      }
+      rho_old = rho;
+      its++;
+      fresh = 0;
+      const double est = vnorm(N, r) / bnorm;
+      st->est = est;
+      if (hist) hist[its - 1] = est;
+      if (!isfinite(est)) { st->breakdown = 1; break; }
+      if (est <= rtol) { restart = 1; break; }
+      if (omega == 0) { restart = 1; break; }
+    }
+    if (st->breakdown) break;
+    if (!restart && its >= max_it) {
+      /* cap reached inside the loop: report the true residual */
+      orc_spmv(A, x, r);
+      for (int64_t i = 0; i < N; i++) r[i] = b[i] - r[i];
+      st->relres = vnorm(N, r) / bnorm;
+      st->converged = st->relres <= rtol;
+      break;
+    }
+  }
+  st->iters = its;
+done:
+  free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
+  free(pc.bj);
+  return st->converged ? 0 : (st->breakdown ? -3 : 1);
+}
+
 /* Dense copy of the block matrix (tiny meshes only) for checks against a
  * textbook dense solver. */
 void orc_dense(const orc_matrix *A, cplx *dense) {

@@ -99,6 +99,9 @@ def lib():
         L.orc_gmres.argtypes = [vp, C.c_int, C.c_double, PCFN, vp, vp, vp, C.c_int, C.c_int,
                                 C.c_double, C.c_int, C.POINTER(Stats), vp]
         L.orc_gmres.restype = C.c_int
+        L.orc_bicgstab.argtypes = [vp, C.c_int, C.c_double, PCFN, vp, vp, vp, C.c_int, C.c_double,
+                                   C.POINTER(Stats), vp]
+        L.orc_bicgstab.restype = C.c_int
         L.orc_dense.argtypes = [vp, vp]
         L.orc_dense_solve.argtypes = [i64, vp, vp]
         L.orc_dense_solve.restype = C.c_int
@@ -232,6 +235,36 @@ class Matrix:
         if history:
             info["history"] = hist[:st.iters].copy()
         return x, info
+
+
+def _pc_callback(N, pc, pcfn):
+    kind = {"none": 0, "bj": 1, "spectral": 2, "fn": 3}[pc]
+    cb = PCFN(0)
+    if kind == 3:
+        def _cb(pin, pout, ctx):
+            vin = np.ctypeslib.as_array(C.cast(pin, C.POINTER(C.c_double)), shape=(2 * N,))
+            vout = np.ctypeslib.as_array(C.cast(pout, C.POINTER(C.c_double)), shape=(2 * N,))
+            z = pcfn(vin.view(np.complex128).copy())
+            vout[:] = np.ascontiguousarray(z, np.complex128).view(np.float64)
+        cb = PCFN(_cb)
+    return kind, cb
+
+
+def bicgstab(A: "Matrix", b, x0=None, max_it=20000, rtol=1e-8, pc="bj", vbar=0.0, pcfn=None, history=False):
+    """BiCGSTAB with right preconditioning (the paper's second solver, Sec. 4.4;
+    van der Vorst 1992), restarting from the true residual when the updated one
+    has drifted.  pc as for Matrix.gmres."""
+    b = np.ascontiguousarray(b, np.complex128)
+    x = np.zeros(A.N, np.complex128) if x0 is None else np.array(x0, np.complex128)
+    kind, cb = _pc_callback(A.N, pc, pcfn)
+    st = Stats()
+    hist = np.zeros(max(max_it, 1), np.float64)
+    rc = lib().orc_bicgstab(A.h, kind, vbar, cb, None, _ptr(b), _ptr(x), max_it, rtol, C.byref(st), _ptr(hist))
+    info = dict(rc=rc, iters=st.iters, restarts=st.restarts, converged=bool(st.converged),
+                breakdown=bool(st.breakdown), relres=st.relres, est=st.est)
+    if history:
+        info["history"] = hist[:st.iters].copy()
+    return x, info
 
 
 def row(p: Problem, r: int):
