@@ -389,6 +389,25 @@ def main():
     obj = D.make_opts(restart=m, max_it=100, pc="bj", precision=64, rtol=rtol)
     ms_bj, info_bj = solve(obj)
 
+    # BiCGSTAB (the paper's second solver): with the step's preconditioner, and
+    # the 100-iteration window with node-block Jacobi
+    def solve_bi(o):
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        try:
+            _, inf = D.bicgstab(op, b, x, opts=o)
+        except D.DiracError as e:  # a non-finite residual ends the window
+            inf = {"iters": -1, "relres": float("nan"), "error": str(e)}
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, inf
+    obi = D.make_opts(max_it=args.max_it, pc=o64.pc, vbar=o64.vbar, precision=64, rtol=rtol)
+    solve_bi(obi)
+    ms_bi, info_bi = solve_bi(obi)
+    obibj = D.make_opts(max_it=100, pc="bj", precision=64, rtol=rtol)
+    solve_bi(obibj)
+    ms_bibj, info_bibj = solve_bi(obibj)
+
     # kernels on their own (HIP events on the launch stream)
     reps = args.kernel_reps
     xx = torch.randn(op.n, dtype=torch.complex128, device="cuda")
@@ -441,6 +460,10 @@ def main():
             "step_relres": info_step["relres"], "step_iters": info_step["iters"],
             "plain_bj_100it_ms": round(ms_bj, 3), "plain_bj_100it_relres": info_bj["relres"],
             "plain_bj_ms_per_iter": round(ms_bj / max(info_bj["iters"], 1), 4),
+            "bicgstab_ms": round(ms_bi, 3), "bicgstab_iters": info_bi["iters"],
+            "bicgstab_relres": info_bi["relres"],
+            "bicgstab_bj_100it_ms": round(ms_bibj, 3), "bicgstab_bj_100it_relres": info_bibj["relres"],
+            "bicgstab_bj_ms_per_iter": round(ms_bibj / max(info_bibj["iters"], 1), 4),
         },
         "kernels_ms": {"spmv_c128": round(t_spmv64, 4), "spmv_c64": round(t_spmv32, 4),
                        "assemble": round(t_asm, 4), "spectral_pc_c64": round(t_pc32, 4)},

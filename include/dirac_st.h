@@ -279,6 +279,29 @@ size_t dirac_st_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *opts
 int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_opts *opts,
                    void *work, size_t work_bytes, dirac_st_stats *stats, void *stream);
 
+/* Bytes of device workspace needed by dirac_st_bicgstab for these options:
+ * eight complex128 vectors, partial sums, scalars, preconditioner data.
+ * Returns 0 for an invalid matrix. */
+size_t dirac_st_bicgstab_workspace_bytes(const dirac_st_bsr *A, const dirac_st_opts *opts);
+
+/* BiCGSTAB, the second Krylov solver of the paper's parallel runs (Sec. 4.4,
+ * Tables 1-3; van der Vorst's algorithm), right-preconditioned so that r is
+ * the residual of A x = b, in complex128 (opts->precision must be 64).  Per
+ * iteration two products with A and two preconditioner applications; the
+ * scalars stay on the device and the host reads 16 bytes per iteration.  The
+ * stop test uses the updated residual; when it passes, the FP64 true
+ * residual decides, and a drifted residual (or a zero rh^H v, rho or omega)
+ * restarts the iteration from the true residual.  opts: max_it caps the
+ * iterations, max_cycles the starts (0 = no cap), rtol, pc, vbar,
+ * time_slabs; restart and inner_rtol are ignored.  b, x as for
+ * dirac_st_gmres (x: initial guess on entry).  stats->cycles counts the
+ * starts, stats->history receives ||r|| / ||b|| per iteration.  Returns
+ * DIRAC_ST_OK, DIRAC_ST_NOT_CONVERGED, DIRAC_ST_EBREAKDOWN (NaN/Inf, or a
+ * restart that breaks down again before one iteration completes),
+ * DIRAC_ST_ENOSPACE or DIRAC_ST_EINVAL. */
+int dirac_st_bicgstab(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_opts *opts,
+                      void *work, size_t work_bytes, dirac_st_stats *stats, void *stream);
+
 /* Host.  Generalised eigen-decomposition of the Galerkin time pencil used by
  * DIRAC_ST_PC_LINE: the n_t x n_t factors of the t = 1..n_t rows and columns
  * (Sec. 2.1 weak form with the t = 0 node moved to the right-hand side; App. A

@@ -69,6 +69,10 @@ _lib.dirac_st_gmres.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, 
                                 C.POINTER(Stats), _vp]
 
 _lib.dirac_st_nn_param_count.restype = C.c_size_t
+_lib.dirac_st_bicgstab_workspace_bytes.argtypes = [C.POINTER(BSR), C.POINTER(Opts)]
+_lib.dirac_st_bicgstab_workspace_bytes.restype = C.c_size_t
+_lib.dirac_st_bicgstab.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, C.c_size_t,
+                                   C.POINTER(Stats), _vp]
 _lib.dirac_st_nn_workspace_bytes.argtypes = [_i32, _i32, _i32, _i32]
 _lib.dirac_st_nn_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_nn_pack.argtypes = [C.POINTER(NNStruct), _vp]
@@ -104,7 +108,8 @@ EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_
            "dirac_st_fgmres_nn", "dirac_st_batched_workspace_bytes", "dirac_st_fgmres_batched",
            "dirac_st_spmv_batched_workspace_bytes", "dirac_st_spmv_batched",
            "dirac_st_batched_set_lanes", "dirac_st_batched_lanes", "dirac_st_time_eigen",
-           "dirac_st_timing", "dirac_st_timing_read"]
+           "dirac_st_timing", "dirac_st_timing_read", "dirac_st_bicgstab_workspace_bytes",
+           "dirac_st_bicgstab"]
 
 
 class DiracError(RuntimeError):
@@ -274,6 +279,33 @@ def gmres(op: Operator, b: torch.Tensor, x: torch.Tensor | None = None, opts: Op
     _check(rc, allow=(OK, NOT_CONVERGED))
     info = dict(rc=rc, iters=st.iters, cycles=st.cycles, converged=bool(st.converged),
                 relres=st.relres, est=st.est, ms=st.ms, singular_blocks=st.singular_blocks)
+    if hist is not None:
+        info["history"] = [hist[i] for i in range(min(st.iters, history))]
+    return x, info
+
+
+def bicgstab(op: Operator, b: torch.Tensor, x: torch.Tensor | None = None, opts: Opts | None = None,
+             work: torch.Tensor | None = None, history: int = 0, **kw):
+    """dirac_st_bicgstab (complex128).  Returns (x, stats dict); kw build the
+    options when opts is None (restart is ignored)."""
+    if opts is None:
+        opts = make_opts(**kw)
+    if x is None:
+        x = torch.zeros_like(b)
+    if work is None:
+        nbytes = int(_lib.dirac_st_bicgstab_workspace_bytes(C.byref(op.bsr), C.byref(opts)))
+        work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=b.device)
+    st = Stats()
+    hist = None
+    if history:
+        hist = (C.c_double * history)()
+        st.history = C.cast(hist, C.POINTER(C.c_double))
+        st.history_len = history
+    rc = _lib.dirac_st_bicgstab(C.byref(op.bsr), _ptr(b), _ptr(x), C.byref(opts), _ptr(work), work.numel(),
+                                C.byref(st), _stream())
+    _check(rc, allow=(OK, NOT_CONVERGED))
+    info = dict(rc=rc, iters=st.iters, cycles=st.cycles, converged=bool(st.converged),
+                relres=st.relres, est=st.est, ms=st.ms)
     if hist is not None:
         info["history"] = [hist[i] for i in range(min(st.iters, history))]
     return x, info
