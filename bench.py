@@ -385,6 +385,11 @@ def main():
     ms32, info32b = solve(o32)
     x32 = x.clone()
 
+    # the same complex128 solve with the matrix-free operator
+    omf = D.make_opts(restart=m, max_it=2000, pc=o64.pc, vbar=o64.vbar, precision=64, rtol=rtol, matrix_free=True)
+    solve(omf)
+    ms_mf, info_mf = solve(omf)
+
     # plain GMRES(50) with node-block Jacobi: the 100-iteration window
     obj = D.make_opts(restart=m, max_it=100, pc="bj", precision=64, rtol=rtol)
     ms_bj, info_bj = solve(obj)
@@ -418,6 +423,10 @@ def main():
     t_asm = time_launches(lambda: D.assemble_into(op, psi0, b), max(reps // 4, 2), torch)
     pcw = torch.empty(D.workspace_bytes(op, o32), dtype=torch.uint8, device="cuda")
     t_pc32 = time_launches(lambda: D.pc_apply(op, xx32, "spectral", 0.0, yy32, pcw), max(reps // 4, 2), torch)
+    # the matrix-free operator: x read and y written once (the stencil
+    # coefficients are computed, not read)
+    t_mf64 = time_launches(lambda: D.spmv_mf(op, xx, yy), reps, torch)
+    t_mf32 = time_launches(lambda: D.spmv_mf(op, xx32, yy32), reps, torch)
     by64, by32 = spmv_bytes(op, 16), spmv_bytes(op, 8)
     gbs64, gbs32 = by64 / t_spmv64 / 1e6, by32 / t_spmv32 / 1e6
     asm_bytes = op.bytes() + op.n * 16 + psi0.numel() * 16
@@ -460,13 +469,16 @@ def main():
             "step_relres": info_step["relres"], "step_iters": info_step["iters"],
             "plain_bj_100it_ms": round(ms_bj, 3), "plain_bj_100it_relres": info_bj["relres"],
             "plain_bj_ms_per_iter": round(ms_bj / max(info_bj["iters"], 1), 4),
+            "fp64_matrix_free_ms": round(ms_mf, 3), "fp64_matrix_free_iters": info_mf["iters"],
+            "fp64_matrix_free_relres": info_mf["relres"],
             "bicgstab_ms": round(ms_bi, 3), "bicgstab_iters": info_bi["iters"],
             "bicgstab_relres": info_bi["relres"],
             "bicgstab_bj_100it_ms": round(ms_bibj, 3), "bicgstab_bj_100it_relres": info_bibj["relres"],
             "bicgstab_bj_ms_per_iter": round(ms_bibj / max(info_bibj["iters"], 1), 4),
         },
         "kernels_ms": {"spmv_c128": round(t_spmv64, 4), "spmv_c64": round(t_spmv32, 4),
-                       "assemble": round(t_asm, 4), "spectral_pc_c64": round(t_pc32, 4)},
+                       "assemble": round(t_asm, 4), "spectral_pc_c64": round(t_pc32, 4),
+                       "spmv_matrix_free_c128": round(t_mf64, 4), "spmv_matrix_free_c64": round(t_mf32, 4)},
         "spmv": {"c128_GBps": round(gbs64, 1), "c64_GBps": round(gbs32, 1),
                  "c128_frac": round(gbs64 / HBM_PEAK_GBS, 4), "c64_frac": round(gbs32 / HBM_PEAK_GBS, 4),
                  "c128_bytes": by64, "c64_bytes": by32},
@@ -485,7 +497,12 @@ def main():
             "assemble": None if l_asm is None else
             {"bound": "hbm", "avg_launch_ms": round(l_asm, 4), "launches_timed": n_asm,
              "algorithmic_bytes": asm_bytes, "achieved": round(asm_bytes / l_asm / 1e6, 1),
-             "frac": round(asm_bytes / l_asm / 1e6 / HBM_PEAK_GBS, 4)}},
+             "frac": round(asm_bytes / l_asm / 1e6 / HBM_PEAK_GBS, 4)},
+            "spmv_matrix_free_c128": {"bound": "hbm", "avg_launch_ms": round(t_mf64, 4),
+                                      "algorithmic_bytes": 2 * op.n * 16,
+                                      "achieved": round(2 * op.n * 16 / t_mf64 / 1e6, 1),
+                                      "frac": round(2 * op.n * 16 / t_mf64 / 1e6 / HBM_PEAK_GBS, 4),
+                                      "speedup_vs_stored_blocks": round(t_spmv64 / t_mf64, 2)}},
         "assembly": {"ms": round(t_asm, 4), "bytes_written": asm_bytes,
                      "GBps": round(asm_bytes / t_asm / 1e6, 1)},
         "memory_GB": round((op.bytes() + work.numel()) / 1e9, 3),

@@ -146,6 +146,12 @@ typedef struct {
   double vbar;        /* constant potential of DIRAC_ST_PC_SPECTRAL */
   int32_t time_slabs; /* DIRAC_ST_PC_TIME_SLABS: number of time slabs (>= 1,
                          divides n_t); ignored by the other preconditioners */
+  int32_t matrix_free; /* dirac_st_gmres / dirac_st_bicgstab: 1 applies the
+                          operator from A->prob with the matrix-free stencil
+                          (dirac_st_spmv_mf) instead of the stored blocks, in
+                          every product and residual; the value arrays of A
+                          are then not read and may be NULL (node-block
+                          Jacobi still needs bjinv64/32).  0: stored blocks. */
 } dirac_st_opts;
 
 typedef struct {
@@ -250,6 +256,21 @@ int dirac_st_assemble(const dirac_st_problem *prob, const void *psi0, dirac_st_b
  * row_ptr / col_idx are not read; 4x4 blocks use them. */
 int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x, void *y, void *stream);
 
+/* y = A x without a stored matrix: the operator of problem p (the one
+ * dirac_st_assemble builds, Sec. 2.1-2.2 and App. A, potential of Sec. 4.3)
+ * applied as a sum of Kronecker products of 1D three-point stencils, one
+ * thread per row node, x staged in LDS per tile for d <= 2.  Equal to
+ * dirac_st_spmv on the assembled matrix up to rounding order.  x, y: device,
+ * [nrows][nc] complex128 (prec 64) or complex64 (prec 32), not overlapping.
+ * Enqueues on `stream`; DIRAC_ST_EINVAL for an invalid problem or arguments. */
+int dirac_st_spmv_mf(const dirac_st_problem *p, int32_t prec, const void *x, void *y, void *stream);
+
+/* b = -D_w21 psi0 (Sec. 2.1, eq. (dirac_weakIVP)) without a stored matrix:
+ * the right-hand side dirac_st_assemble writes, from the same stencils.
+ * psi0: device, [S][nc] complex128 (the t = 0 slice); b: device,
+ * [nrows][nc] complex128, zero outside tau = 1.  Enqueues on `stream`. */
+int dirac_st_rhs_mf(const dirac_st_problem *p, const void *psi0, void *b, void *stream);
+
 /* z = M^{-1} v for the preconditioner opts->pc (DIRAC_ST_PC_*, not NONE) in
  * precision opts->precision (64: complex128, 32: complex64), with its
  * parameters opts->vbar / opts->time_slabs.  work: workspace of at least
@@ -322,7 +343,8 @@ enum {
   DIRAC_ST_TIMED_SPMV32 = 1,   /* y = A x, complex64 */
   DIRAC_ST_TIMED_RESID64 = 2,  /* r = b - A x, complex128 (the FP64 true residual) */
   DIRAC_ST_TIMED_ASSEMBLE = 3, /* the block-CSR assembly kernel */
-  DIRAC_ST_TIMED_COUNT = 4
+  DIRAC_ST_TIMED_SPMV_MF = 4,  /* the matrix-free operator, any precision or form */
+  DIRAC_ST_TIMED_COUNT = 5
 };
 
 /* Host.  on = 1 starts recording (earlier records are dropped), on = 0 stops.

@@ -36,34 +36,6 @@ struct AsmParams {
   int64_t off_int, off_last;
 };
 
-static void gamma_set(int d, double2 (*g)[16]) {
-  for (int mu = 0; mu < 4; mu++)
-    for (int q = 0; q < 16; q++) g[mu][q] = mk<double2>(0, 0);
-  if (d <= 2) {
-    // g0 = diag(1, -1), g1 = [[0, 1], [-1, 0]] (App. A); g2 = [[0, -i], [-i, 0]]
-    g[0][0] = mk<double2>(1, 0);
-    g[0][3] = mk<double2>(-1, 0);
-    g[1][1] = mk<double2>(1, 0);
-    g[1][2] = mk<double2>(-1, 0);
-    g[2][1] = mk<double2>(0, -1);
-    g[2][2] = mk<double2>(0, -1);
-    return;
-  }
-  // Dirac representation: g0 = diag(I, -I), gk = [[0, s_k], [-s_k, 0]]
-  for (int q = 0; q < 4; q++) g[0][q * 5] = mk<double2>(q < 2 ? 1 : -1, 0);
-  const double2 pauli[3][4] = {
-      {mk<double2>(0, 0), mk<double2>(1, 0), mk<double2>(1, 0), mk<double2>(0, 0)},
-      {mk<double2>(0, 0), mk<double2>(0, -1), mk<double2>(0, 1), mk<double2>(0, 0)},
-      {mk<double2>(1, 0), mk<double2>(0, 0), mk<double2>(0, 0), mk<double2>(-1, 0)}};
-  for (int k = 1; k <= 3; k++)
-    for (int a = 0; a < 2; a++)
-      for (int b = 0; b < 2; b++) {
-        double2 s = pauli[k - 1][a * 2 + b];
-        g[k][a * 4 + b + 2] = s;
-        g[k][(a + 2) * 4 + b] = mk<double2>(-s.x, -s.y);
-      }
-}
-
 static AsmParams make_params(const dirac_st_problem *p) {
   AsmParams P{};
   P.d = p->d;

@@ -943,6 +943,7 @@ static int check_batch_opts(int32_t nsys, const dirac_st_bsr *const *A, const di
   DST_CHECK(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in 1..%d", kMaxRestart);
   DST_CHECK(o->precision == 64 || o->precision == 32, "precision must be 64 or 32");
   DST_CHECK(o->rtol > 0.0 && o->max_it >= 0, "rtol must be positive and max_it >= 0");
+  DST_CHECK(o->matrix_free == 0, "the batched solver applies the stored blocks (matrix_free must be 0)");
   for (int i = 0; i < nsys; i++) {
     if (int rc = check_pc_opts(A[i], o)) return rc;
     DST_CHECK(A[i]->prob.d == A[0]->prob.d, "all systems of a batched solve must have the same dimension");

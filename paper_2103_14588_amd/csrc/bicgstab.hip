@@ -23,6 +23,7 @@
 #include "common.hpp"
 #include "krylov.hpp"
 #include "precond.hpp"
+#include "mfspmv.hpp"
 #include "spmv.hpp"
 
 namespace dst {
@@ -229,6 +230,7 @@ static int bicgstab_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, co
   double2 *r = (double2 *)(work + L.r), *rh = (double2 *)(work + L.rh), *p = (double2 *)(work + L.p);
   double2 *v = (double2 *)(work + L.v), *sv = (double2 *)(work + L.s), *t = (double2 *)(work + L.t);
   const bool pcon = o->pc != DIRAC_ST_PC_NONE;
+  const bool mf = o->matrix_free != 0;
   double2 *ph = pcon ? (double2 *)(work + L.ph) : p;
   double2 *sh = pcon ? (double2 *)(work + L.sh) : sv;
   double2 *partial = (double2 *)(work + L.partial);
@@ -278,7 +280,7 @@ static int bicgstab_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, co
       DST_HIP(hipMemcpyAsync(r, b, (size_t)N * sizeof(double2), hipMemcpyDeviceToDevice, s));
       x_zero = false;
     } else {
-      DST_HIP(launch_spmv_st<double>(A, A->val64, x, b, r, 1.0, true, s));
+      DST_HIP(apply_op<double>(A, mf, A->val64, x, b, r, 1.0, true, s));
     }
     double rn2 = 0.0;
     if (int rc = norm2(r, rn2)) return rc;
@@ -310,14 +312,14 @@ static int bicgstab_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, co
       first = false;
       if (pcon)
         if (int rc = pc_apply_base<double>(P, p, ph, 1.0, N, s)) return rc;
-      DST_HIP(launch_spmv_st<double>(A, A->val64, ph, nullptr, v, 1.0, false, s));
+      DST_HIP(apply_op<double>(A, mf, A->val64, ph, nullptr, v, 1.0, false, s));
       bi_dot<false><<<g, 256, 0, s>>>(rh, v, partial, N, nblk);
       bi_reduce<1><<<1, 256, 0, s>>>(partial, nblk, c, 0);
       bi_s<<<g, 256, 0, s>>>(r, v, sv, c, N);
       DST_LAUNCHED();
       if (pcon)
         if (int rc = pc_apply_base<double>(P, sv, sh, 1.0, N, s)) return rc;
-      DST_HIP(launch_spmv_st<double>(A, A->val64, sh, nullptr, t, 1.0, false, s));
+      DST_HIP(apply_op<double>(A, mf, A->val64, sh, nullptr, t, 1.0, false, s));
       bi_dot<true><<<g, 256, 0, s>>>(t, sv, partial, N, nblk);
       bi_reduce<2><<<1, 256, 0, s>>>(partial, nblk, c, 1);
       bi_update<<<g, 256, 0, s>>>(x, r, ph, sh, sv, t, rh, c, partial, N, nblk);
@@ -365,10 +367,17 @@ extern "C" int dirac_st_bicgstab(const dirac_st_bsr *A, const void *b, void *x, 
                                  void *work, size_t work_bytes, dirac_st_stats *stats, void *stream) {
   clear_error();
   DST_CHECK(A != nullptr, "matrix is NULL");
-  DST_CHECK(A->row_ptr && A->col_idx && A->val64, "matrix arrays are NULL");
-  DST_CHECK(A->nc == 2 || A->nc == 4, "matrix nc must be 2 or 4 (was it assembled?)");
-  DST_CHECK(A->nrows > 0 && A->nnzb > 0, "empty matrix");
   DST_CHECK(opts != nullptr, "opts is NULL");
+  if (opts->matrix_free) {
+    if (int rc = validate_problem(&A->prob)) return rc;
+    int64_t rows = A->prob.n[0];
+    for (int a = 1; a <= A->prob.d; a++) rows *= A->prob.n[a];
+    DST_CHECK(A->nc == A->prob.nc && A->nrows == rows, "A->nc / A->nrows must match A->prob");
+  } else {
+    DST_CHECK(A->row_ptr && A->col_idx && A->val64, "matrix arrays are NULL");
+    DST_CHECK(A->nc == 2 || A->nc == 4, "matrix nc must be 2 or 4 (was it assembled?)");
+    DST_CHECK(A->nrows > 0 && A->nnzb > 0, "empty matrix");
+  }
   DST_CHECK(b && x && work, "b, x and work must be set");
   DST_CHECK(opts->precision == 64, "BiCGSTAB runs in complex128 (precision 64)");
   if (int rc = check_pc_opts(A, opts)) return rc;

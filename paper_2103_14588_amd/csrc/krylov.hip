@@ -24,6 +24,7 @@
 #include "nn_host.hpp"
 #include "precond.hpp"
 #include "spectral.hpp"
+#include "mfspmv.hpp"
 #include "spmv.hpp"
 
 namespace dst {
@@ -181,6 +182,7 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   C *Zb = (C *)(work + L.Z);
   const int64_t nblk = nblocks(N);
   const void *val = sizeof(T) == 8 ? A->val64 : A->val32;
+  const bool mf = o->matrix_free != 0;
 
   Precond P;
   if (int rc = pc_setup<T>(P, A, o->pc, o->vbar, work + L.spec, s, pc_slabs(o))) return rc;
@@ -251,7 +253,7 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       rn = bnorm;
       x_zero = false;
     } else {
-      DST_HIP(launch_spmv_st<double>(A, A->val64, x, b, rbuf, 1.0, true, s));
+      DST_HIP(apply_op<double>(A, mf, A->val64, x, b, rbuf, 1.0, true, s));
       if (int rc = read_norm(rbuf, rn)) return rc;
     }
     S.relres = rn / bnorm;
@@ -288,17 +290,17 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       C *w = V + (int64_t)(j + 1) * L.ldv;
       // w = A M^{-1} v_j
       if (P.kind == DIRAC_ST_PC_NONE && !P.nn_on && !flexible) {
-        DST_HIP(launch_spmv_st<T>(A, val, vj, nullptr, w, (T)sigma_j, false, s));
+        DST_HIP(apply_op<T>(A, mf, val, vj, nullptr, w, (T)sigma_j, false, s));
       } else if (P.kind == DIRAC_ST_PC_NONE && !P.nn_on) {
         // flexible without any preconditioner: z_j = v_j
         C *zj = Zb + (int64_t)j * L.ldv;
         scale_copy<T><<<nblocks(N), 256, 0, s>>>(vj, sigma_j, zj, N);
         DST_LAUNCHED();
-        DST_HIP(launch_spmv_st<T>(A, val, zj, nullptr, w, (T)1, false, s));
+        DST_HIP(apply_op<T>(A, mf, val, zj, nullptr, w, (T)1, false, s));
       } else {
         C *zj = flexible ? Zb + (int64_t)j * L.ldv : z;
         if (int rc = pc_apply<T>(P, vj, zj, sigma_j, N, s)) return rc;
-        DST_HIP(launch_spmv_st<T>(A, val, zj, nullptr, w, (T)1, false, s));
+        DST_HIP(apply_op<T>(A, mf, val, zj, nullptr, w, (T)1, false, s));
       }
       const int jp1 = j + 1, mk = maxk_bucket(jp1);
       // pass 1: h1 = V^H w
@@ -378,6 +380,20 @@ static int check_bsr(const dirac_st_bsr *A) {
   return 0;
 }
 
+// solvers: with the matrix-free operator only the problem (and the row count
+// it implies) must be valid
+static int check_solver_matrix(const dirac_st_bsr *A, const dirac_st_opts *o) {
+  DST_CHECK(A != nullptr, "matrix is NULL");
+  DST_CHECK(o != nullptr, "opts is NULL");
+  if (!o->matrix_free) return check_bsr(A);
+  if (int rc = validate_problem(&A->prob)) return rc;
+  DST_CHECK(A->nc == A->prob.nc, "A->nc must equal prob.nc");
+  int64_t rows = A->prob.n[0];
+  for (int a = 1; a <= A->prob.d; a++) rows *= A->prob.n[a];
+  DST_CHECK(A->nrows == rows, "A->nrows must be the row count of A->prob");
+  return 0;
+}
+
 }  // namespace dst
 
 using namespace dst;
@@ -396,6 +412,33 @@ extern "C" int dirac_st_spmv(const dirac_st_bsr *A, int32_t prec, const void *x,
     DST_HIP(launch_spmv_st<double>(A, A->val64, x, nullptr, y, 1.0, false, s));
   else
     DST_HIP(launch_spmv_st<float>(A, A->val32, x, nullptr, y, 1.0f, false, s));
+  return DIRAC_ST_OK;
+}
+
+extern "C" int dirac_st_spmv_mf(const dirac_st_problem *p, int32_t prec, const void *x, void *y, void *stream) {
+  clear_error();
+  DST_CHECK(p != nullptr, "problem is NULL");
+  if (int rc = validate_problem(p)) return rc;
+  DST_CHECK(prec == 64 || prec == 32, "prec must be 64 or 32");
+  DST_CHECK(x && y, "x and y must be set");
+  DST_CHECK(x != y, "x and y must not overlap");
+  const size_t al = prec == 64 ? 16 : 8;
+  DST_CHECK(((uintptr_t)x % al) == 0 && ((uintptr_t)y % al) == 0, "x, y must be aligned to their element size");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == 64)
+    DST_HIP(launch_spmv_mf<double>(p, x, nullptr, y, 1.0, false, s));
+  else
+    DST_HIP(launch_spmv_mf<float>(p, x, nullptr, y, 1.0f, false, s));
+  return DIRAC_ST_OK;
+}
+
+extern "C" int dirac_st_rhs_mf(const dirac_st_problem *p, const void *psi0, void *b, void *stream) {
+  clear_error();
+  DST_CHECK(p != nullptr, "problem is NULL");
+  if (int rc = validate_problem(p)) return rc;
+  DST_CHECK(psi0 && b, "psi0 and b must be set");
+  DST_CHECK(((uintptr_t)psi0 & 15) == 0 && ((uintptr_t)b & 15) == 0, "psi0, b must be 16-byte aligned");
+  DST_HIP(launch_rhs_mf(p, psi0, b, (hipStream_t)stream));
   return DIRAC_ST_OK;
 }
 
@@ -443,13 +486,13 @@ extern "C" int dirac_st_gmres(const dirac_st_bsr *A, const void *b, void *x,
                               const dirac_st_opts *opts, void *work, size_t work_bytes,
                               dirac_st_stats *stats, void *stream) {
   clear_error();
-  if (int rc = check_bsr(A)) return rc;
   DST_CHECK(opts != nullptr, "opts is NULL");
+  if (int rc = check_solver_matrix(A, opts)) return rc;
   DST_CHECK(b && x && work, "b, x and work must be set");
   DST_CHECK(opts->restart >= 1 && opts->restart <= kMaxRestart, "restart must be in 1..%d",
             kMaxRestart);
   DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
-  DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
+  DST_CHECK(opts->precision == 64 || A->val32 || opts->matrix_free, "precision 32 needs val32");
   if (int rc = check_pc_opts(A, opts)) return rc;
   DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
   DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");
@@ -475,13 +518,13 @@ extern "C" int dirac_st_fgmres_nn(const dirac_st_bsr *A, const void *b, void *x,
                                   const dirac_st_nn *net, const dirac_st_opts *opts, void *work,
                                   size_t work_bytes, dirac_st_stats *stats, void *stream) {
   clear_error();
-  if (int rc = check_bsr(A)) return rc;
   DST_CHECK(opts != nullptr, "opts is NULL");
+  if (int rc = check_solver_matrix(A, opts)) return rc;
   DST_CHECK(b && x && work, "b, x and work must be set");
   DST_CHECK(opts->restart >= 1 && opts->restart <= kMaxRestart, "restart must be in 1..%d",
             kMaxRestart);
   DST_CHECK(opts->precision == 64 || opts->precision == 32, "precision must be 64 or 32");
-  DST_CHECK(opts->precision == 64 || A->val32, "precision 32 needs val32");
+  DST_CHECK(opts->precision == 64 || A->val32 || opts->matrix_free, "precision 32 needs val32");
   if (int rc = check_pc_opts(A, opts)) return rc;
   DST_CHECK(opts->rtol > 0.0, "rtol must be positive");
   DST_CHECK(opts->max_it >= 0, "max_it must be >= 0");

@@ -73,29 +73,7 @@ static void spec_geom(const dirac_st_problem *p, double vbar, SpecGeom &G) {
   }
   G.m = p->m;
   G.vbar = vbar;
-  for (int mu = 0; mu < 4; mu++)
-    for (int q = 0; q < 16; q++) G.g[mu][q] = mk<double2>(0, 0);
-  if (p->d <= 2) {
-    G.g[0][0] = mk<double2>(1, 0);
-    G.g[0][3] = mk<double2>(-1, 0);
-    G.g[1][1] = mk<double2>(1, 0);
-    G.g[1][2] = mk<double2>(-1, 0);
-    G.g[2][1] = mk<double2>(0, -1);
-    G.g[2][2] = mk<double2>(0, -1);
-  } else {
-    for (int q = 0; q < 4; q++) G.g[0][q * 5] = mk<double2>(q < 2 ? 1 : -1, 0);
-    const double2 P[3][4] = {
-        {mk<double2>(0, 0), mk<double2>(1, 0), mk<double2>(1, 0), mk<double2>(0, 0)},
-        {mk<double2>(0, 0), mk<double2>(0, -1), mk<double2>(0, 1), mk<double2>(0, 0)},
-        {mk<double2>(1, 0), mk<double2>(0, 0), mk<double2>(0, 0), mk<double2>(-1, 0)}};
-    for (int k = 1; k <= 3; k++)
-      for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++) {
-          double2 s = P[k - 1][a * 2 + b];
-          G.g[k][a * 4 + b + 2] = s;
-          G.g[k][(a + 2) * 4 + b] = mk<double2>(-s.x, -s.y);
-        }
-  }
+  gamma_set(p->d, G.g);
 }
 
 // Twiddles exp(-2 pi i q / n_a) of every spatial axis, FP64 and FP32 copies,

@@ -42,7 +42,8 @@ class BSR(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_it", C.c_int32), ("pc", C.c_int32),
                 ("precision", C.c_int32), ("max_cycles", C.c_int32), ("rtol", C.c_double),
-                ("inner_rtol", C.c_double), ("vbar", C.c_double), ("time_slabs", C.c_int32)]
+                ("inner_rtol", C.c_double), ("vbar", C.c_double), ("time_slabs", C.c_int32),
+                ("matrix_free", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -69,6 +70,8 @@ _lib.dirac_st_gmres.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, 
                                 C.POINTER(Stats), _vp]
 
 _lib.dirac_st_nn_param_count.restype = C.c_size_t
+_lib.dirac_st_spmv_mf.argtypes = [C.POINTER(Problem), _i32, _vp, _vp, _vp]
+_lib.dirac_st_rhs_mf.argtypes = [C.POINTER(Problem), _vp, _vp, _vp]
 _lib.dirac_st_bicgstab_workspace_bytes.argtypes = [C.POINTER(BSR), C.POINTER(Opts)]
 _lib.dirac_st_bicgstab_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_bicgstab.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, C.c_size_t,
@@ -109,7 +112,7 @@ EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_
            "dirac_st_spmv_batched_workspace_bytes", "dirac_st_spmv_batched",
            "dirac_st_batched_set_lanes", "dirac_st_batched_lanes", "dirac_st_time_eigen",
            "dirac_st_timing", "dirac_st_timing_read", "dirac_st_bicgstab_workspace_bytes",
-           "dirac_st_bicgstab"]
+           "dirac_st_bicgstab", "dirac_st_spmv_mf", "dirac_st_rhs_mf"]
 
 
 class DiracError(RuntimeError):
@@ -230,6 +233,38 @@ def spmv(op: Operator, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.
     return y
 
 
+def spmv_mf(op_or_spec, x: torch.Tensor, y=None):
+    """dirac_st_spmv_mf: y = A x from the problem alone (an Operator's problem,
+    or a Spec)."""
+    prob = op_or_spec.bsr.prob if isinstance(op_or_spec, Operator) else make_problem(op_or_spec)
+    prec = 64 if x.dtype == torch.complex128 else 32
+    if y is None:
+        y = torch.empty_like(x)
+    _check(_lib.dirac_st_spmv_mf(C.byref(prob), prec, _ptr(x), _ptr(y), _stream()))
+    return y
+
+
+def rhs_mf(spec, psi0: torch.Tensor, b=None):
+    """dirac_st_rhs_mf: b = -D_w21 psi0 from the stencils (no assembly)."""
+    prob = make_problem(spec)
+    nrows, _ = sizes(spec)
+    if b is None:
+        b = torch.empty(nrows * spec.nc, dtype=torch.complex128, device=psi0.device)
+    _check(_lib.dirac_st_rhs_mf(C.byref(prob), _ptr(psi0), _ptr(b), _stream()))
+    return b
+
+
+def problem_operator(spec) -> Operator:
+    """An Operator with no stored arrays: only the problem, nc and the row count,
+    for solves with matrix_free=True."""
+    nrows, nnzb = sizes(spec)
+    bsr = BSR()
+    bsr.nrows, bsr.nnzb, bsr.nc = nrows, nnzb, spec.nc
+    bsr.prob = make_problem(spec)
+    return Operator(spec=spec, bsr=bsr, row_ptr=None, col_idx=None, val64=None, val32=None, bjinv64=None,
+                    bjinv32=None)
+
+
 def pc_apply(op: Operator, v: torch.Tensor, pc="spectral", vbar=0.0, z=None, work=None, slabs=1):
     prec = 64 if v.dtype == torch.complex128 else 32
     kind = PC_NAMES[pc] if isinstance(pc, str) else pc
@@ -247,10 +282,10 @@ def pc_apply(op: Operator, v: torch.Tensor, pc="spectral", vbar=0.0, z=None, wor
 
 
 def make_opts(restart=50, max_it=20000, pc="bj", precision=64, max_cycles=0, rtol=1e-8,
-              inner_rtol=0.0, vbar=0.0, slabs=1) -> Opts:
+              inner_rtol=0.0, vbar=0.0, slabs=1, matrix_free=False) -> Opts:
     return Opts(restart=restart, max_it=max_it, pc=PC_NAMES[pc] if isinstance(pc, str) else pc,
                 precision=precision, max_cycles=max_cycles, rtol=rtol, inner_rtol=inner_rtol,
-                vbar=vbar, time_slabs=slabs)
+                vbar=vbar, time_slabs=slabs, matrix_free=1 if matrix_free else 0)
 
 
 def workspace_bytes(op: Operator, opts: Opts, flexible=False) -> int:
