@@ -125,8 +125,8 @@ def test_spmv_mf_full_size_sampled(D, spec):
 @pytest.mark.parametrize("solver", ["gmres", "bicgstab"])
 def test_solvers_matrix_free_without_stored_arrays(D, solver):
     """Klein step 2+1D: the solve on an operator with no stored arrays
-    (matrix_free) equals the solve with the stored blocks; the spectral
-    preconditioner needs only the problem."""
+    (matrix_free) equals the solve with the stored blocks; the spectral and
+    line preconditioners need only the problem."""
     spec = IN.Spec(d=2, n=[10, 20, 14], vkind=1, v0=2.5, x0=0.5)
     psi = IN.gaussian_packet(spec, [0.3, 0.5], [6.0, 1.0], 0.15, IN.positive_energy_spinor([6.0, 1.0], spec.m, 2))
     op, b = D.assemble(spec, dev(psi))
@@ -134,16 +134,17 @@ def test_solvers_matrix_free_without_stored_arrays(D, solver):
     b_mf = D.rhs_mf(spec, dev(psi))
     assert torch.allclose(b_mf, b, rtol=0, atol=1e-15 * float(b.abs().max()))
     fn = getattr(D, solver)
-    kw = dict(max_it=300, rtol=1e-10, pc="spectral", vbar=1.25)
+    # GMRES with the inexact spectral preconditioner (its iterates agree to
+    # rounding); BiCGSTAB with the exact line preconditioner (its residual
+    # history is too irregular for an iteration count to carry over)
     if solver == "gmres":
-        kw["restart"] = 30
+        kw = dict(max_it=300, rtol=1e-10, pc="spectral", vbar=1.25, restart=30)
+    else:
+        kw = dict(max_it=20, rtol=1e-10, pc="line")
     x1, i1 = fn(op, b, **kw)
     x2, i2 = fn(bare, b_mf, matrix_free=True, **kw)
     assert i1["converged"] and i2["converged"]
-    # GMRES iterates agree to rounding; BiCGSTAB's irregular residual history
-    # turns the rounding difference of the two operators into a few steps
-    slack = 1 if solver == "gmres" else max(2, i1["iters"] // 4)
-    assert abs(i1["iters"] - i2["iters"]) <= slack, (i1, i2)
+    assert abs(i1["iters"] - i2["iters"]) <= (1 if solver == "gmres" else 0), (i1, i2)
     A = O.Matrix(oprob(spec))
     x_ref = np.linalg.solve(A.dense(), A.rhs(psi))
     for xx in (x1, x2):
