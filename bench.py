@@ -296,7 +296,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--only", choices=["spmv64", "spmv32", "assemble", "copy"], default=None,
+    ap.add_argument("--only", choices=["spmv64", "spmv32", "assemble", "copy", "mf64"], default=None,
                     help="launch only this kernel --kernel-reps times (for counter runs)")
     ap.add_argument("--workload", choices=["packet", "packet3", "plane1", "klein", "batch", "slabs"],
                     default="packet",
@@ -336,10 +336,12 @@ def main():
         yy = torch.empty_like(xx)
         xx32, yy32 = xx.to(torch.complex64), torch.empty(op.n, dtype=torch.complex64, device="cuda")
         fn = {"spmv64": lambda: D.spmv(op, xx, yy), "spmv32": lambda: D.spmv(op, xx32, yy32),
-              "assemble": lambda: D.assemble_into(op, psi0, b), "copy": lambda: yy.copy_(xx)}[args.only]
+              "assemble": lambda: D.assemble_into(op, psi0, b), "copy": lambda: yy.copy_(xx),
+              "mf64": lambda: D.spmv_mf(op, xx, yy)}[args.only]
         ms = time_launches(fn, args.kernel_reps, torch)
         nbytes = {"spmv64": spmv_bytes(op, 16), "spmv32": spmv_bytes(op, 8),
-                  "assemble": op.bytes() + op.n * 16 + psi0.numel() * 16, "copy": 2 * op.n * 16}[args.only]
+                  "assemble": op.bytes() + op.n * 16 + psi0.numel() * 16, "copy": 2 * op.n * 16,
+                  "mf64": 2 * op.n * 16}[args.only]
         print(json.dumps({"only": args.only, "reps": args.kernel_reps, "ms": ms, "bytes": nbytes,
                           "GBps": nbytes / ms / 1e6}))
         return

@@ -135,7 +135,19 @@ __global__ __launch_bounds__(256) void bi_reduce(const double2 *__restrict__ par
   for (int k = 0; k < K; k++) {
     double ax = 0.0, ay = 0.0;
     const double2 *p = partial + (int64_t)k * nblk;
-    for (int64_t b = threadIdx.x; b < nblk; b += 256) {
+    int64_t b = threadIdx.x;
+    // eight loads in flight per thread, summed in index order
+    for (; b + 7 * 256 < nblk; b += 8 * 256) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) v[u] = p[b + u * 256];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        ax += v[u].x;
+        ay += v[u].y;
+      }
+    }
+    for (; b < nblk; b += 256) {
       const double2 v = p[b];
       ax += v.x;
       ay += v.y;
