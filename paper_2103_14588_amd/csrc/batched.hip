@@ -500,7 +500,7 @@ static hipError_t launch_g_cgs(int mk, const BSys *S, const WorkList &L, unsigne
     case 16: g_cgs<T, 16, MODE><<<nwg, 256, 0, s>>>(S, L, jp1); break;
     case 32: g_cgs<T, 32, MODE><<<nwg, 256, 0, s>>>(S, L, jp1); break;
     default:
-      if constexpr (MODE != UPDOTS || sizeof(T) == 4) g_cgs<T, 64, MODE><<<nwg, 256, 0, s>>>(S, L, jp1);
+      g_cgs<T, 64, MODE><<<nwg, 256, 0, s>>>(S, L, jp1);
       break;
   }
   return hipGetLastError();
@@ -861,12 +861,7 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
       DST_HIP((launch_g_cgs<T, DOTS>(mk, dS, lists.v, lists.nv, jp1, s)));
       g_reduce<<<dim3(jp1, na), 256, 0, s>>>(dS, lists.w.act, 0, 1);
       DST_LAUNCHED();
-      if (sizeof(T) == 4 || mk <= 32) {
-        DST_HIP((launch_g_cgs<T, UPDOTS>(mk, dS, lists.v, lists.nv, jp1, s)));
-      } else {
-        DST_HIP((launch_g_cgs<T, UPDATE>(mk, dS, lists.v, lists.nv, jp1, s)));
-        DST_HIP((launch_g_cgs<T, DOTS>(mk, dS, lists.v, lists.nv, jp1, s)));
-      }
+      DST_HIP((launch_g_cgs<T, UPDOTS>(mk, dS, lists.v, lists.nv, jp1, s)));
       g_reduce<<<dim3(jp1, na), 256, 0, s>>>(dS, lists.w.act, 0, 2);
       DST_LAUNCHED();
       DST_HIP((launch_g_cgs<T, UPNORM>(mk, dS, lists.v, lists.nv, jp1, s)));

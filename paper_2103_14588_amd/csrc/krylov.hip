@@ -72,11 +72,11 @@ static hipError_t launch_pass_mk(int mk, const cx<T> *V, int64_t ldv, int jp1, c
   return hipGetLastError();
 }
 
-// the fused update + dots pass keeps MAXK basis entries per lane in registers;
-// complex128 stops at 32 of them, larger Gram-Schmidt sets split the pass.
+// the fused update + dots pass handles every Gram-Schmidt set size (the
+// basis entries are re-read for the dots, not held in registers)
 template <typename T>
-static bool fused_updots_ok(int mk) {
-  return sizeof(T) == 4 ? mk <= 64 : mk <= 32;
+static bool fused_updots_ok(int) {
+  return true;
 }
 
 template <typename T>
@@ -87,10 +87,7 @@ static hipError_t launch_updots(int mk, const cx<T> *V, int64_t ldv, int jp1, cx
     case 8: cgs_pass<T, 8, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
     case 16: cgs_pass<T, 16, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
     case 32: cgs_pass<T, 32, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
-    default:
-      if constexpr (sizeof(T) == 4)
-        cgs_pass<T, 64, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n);
-      break;
+    default: cgs_pass<T, 64, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
   }
   return hipGetLastError();
 }

@@ -112,7 +112,6 @@ __device__ __forceinline__ void cgs_block(int64_t blk, int64_t nblk, const cx<T>
     return;
   }
   // update part (coefficients are uniform: scalar loads)
-  C vk[MODE == UPDOTS ? MAXK : 1];
   C acc = we;
 #pragma unroll
   for (int k = 0; k < MAXK; k++) {
@@ -120,9 +119,6 @@ __device__ __forceinline__ void cgs_block(int64_t blk, int64_t nblk, const cx<T>
       C v = in ? V[(int64_t)k * ldv + e] : mk<C>(0, 0);
       const double2 c = coef[k];
       acc = cfms(acc, v, mk<C>((T)c.x, (T)c.y));
-      if (MODE == UPDOTS) vk[k] = v;
-    } else if (MODE == UPDOTS) {
-      vk[k] = mk<C>(0, 0);
     }
   }
   if (in) w[e] = acc;
@@ -138,14 +134,20 @@ __device__ __forceinline__ void cgs_block(int64_t blk, int64_t nblk, const cx<T>
     return;
   }
   if (MODE == UPDOTS) {
-    // products in place, then one butterfly over all MAXK values
+    // products with the updated entry, one butterfly per tile of basis
+    // vectors.  The basis entries are read a second time (the wavefront's
+    // lines are still in the caches) rather than held in registers: holding
+    // them halved the occupancy and cost more than the second read.
     constexpr int KT = MAXK < 32 ? MAXK : 32;
-#pragma unroll
+#pragma unroll 1
     for (int t0 = 0; t0 < MAXK; t0 += KT) {
+      if (t0 >= jp1) break;
       T p[KT][2];
 #pragma unroll
       for (int q = 0; q < KT; q++) {
-        C pr = cfma_conj(mk<C>(0, 0), vk[t0 + q], acc);
+        const int k = t0 + q;
+        const C v = (in && k < jp1) ? V[(int64_t)k * ldv + e] : mk<C>(0, 0);
+        C pr = cfma_conj(mk<C>(0, 0), v, acc);
         p[q][0] = pr.x;
         p[q][1] = pr.y;
       }
