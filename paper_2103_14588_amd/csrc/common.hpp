@@ -113,6 +113,10 @@ void kt_stop(int token, hipStream_t s);
 
 // Rows handled by one XCD stay contiguous: hardware dispatches workgroup b to
 // XCD b % 8, so logical tile = position inside that XCD's share.
+// byte skew between consecutive vectors of a workspace (basis vectors and
+// the like), so that streams read together do not start a power of two apart
+constexpr size_t kVecSkew = 4096;
+
 // Gamma matrices g^mu, row-major nc x nc, for d spatial dimensions.
 inline void gamma_set(int d, double2 (*g)[16]) {
   for (int mu = 0; mu < 4; mu++)
