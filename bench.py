@@ -440,7 +440,7 @@ def main():
     l_res, n_res = live_avg("resid64")
     l_asm, n_asm = live_avg("assemble")
     res_bytes = by64 + op.n * 16  # the residual form also reads b
-    rl_kernel = ("spmv_lds_kernel<double,%d,32,false> (structured block SpMV, x staged in LDS, complex128)" % spec.d
+    rl_kernel = ("spmv_lds_kernel<double,%d,16,2,false> (structured block SpMV, x staged in LDS, complex128)" % spec.d
                  if op.nc == 2 else "spmv_kernel<double,4,64,false> (BSR SpMV, complex128)")
     if l_spmv is None:  # no product in the timed steps: fall back to the isolated launches
         l_spmv, n_spmv = t_spmv64, 0

@@ -264,9 +264,13 @@ inline int64_t st_tiles(const Stencil &g, int rpw) {
 // all their neighbours lie in (time slices) x (3 transverse lines, d = 2) x
 // (RPW + 2 consecutive nodes of axis 1); that tile is loaded once,
 // cooperatively, while the value loads are in flight, and every block then
-// reads its x chunk from LDS instead of gathering it from L2.  Measured 10 %
-// faster than gathering at 2+1D 128^3 in complex128 (73 % of HBM peak).
-template <typename T, int DS, int G, bool RESID>
+// reads its x chunk from LDS instead of gathering it from L2.  G lanes serve
+// RPL consecutive rows (their value loads all issued before the first
+// multiply), so a workgroup owns RPW = 256 / G * RPL rows.  Measured at 2+1D
+// 128^3: 10 % faster than gathering x from L2; G = 16, RPL = 2 (complex128)
+// and G = 8, RPL = 2 (complex64) a further 5-7 % over one row per 32 / 16
+// lanes (76 % and 70 % of HBM peak).
+template <typename T, int DS, int G, int RPL, bool RESID>
 __device__ __forceinline__ void spmv_tile_lds(int64_t tile, const Stencil &g, const cx<T> *__restrict__ val,
                                               const cx<T> *__restrict__ x, const cx<T> *__restrict__ bvec,
                                               cx<T> *__restrict__ y, T alpha) {
@@ -276,7 +280,7 @@ __device__ __forceinline__ void spmv_tile_lds(int64_t tile, const Stencil &g, co
   constexpr int IB = NC / J;          // chunks per x node and per block row
   constexpr int CPB = NC * NC / J;    // chunks per block
   constexpr int BPI = G / CPB;        // blocks per group slice
-  constexpr int RPW = 256 / G;        // rows per workgroup
+  constexpr int RPW = 256 / G * RPL;  // rows per workgroup
   constexpr int IMASK = (NC - 1) * IB;
   constexpr int P = DS == 1 ? 3 : 9;
   constexpr int NY = DS == 1 ? 1 : 3;  // transverse lines
@@ -294,23 +298,25 @@ __device__ __forceinline__ void spmv_tile_lds(int64_t tile, const Stencil &g, co
   const int tau0 = tau >= 2 ? tau - 1 : tau;
   const int ntime = g.nt == 1 ? 1 : ((tau == 1 || tau == g.nt) ? 2 : 3);
   const int lane = threadIdx.x % G;
-  const int xr = x0 + (int)(threadIdx.x / G);
-  const bool own = xr < n1;
-  const int64_t row = line * n1 + xr;
+  const int xr0 = x0 + (int)(threadIdx.x / G) * RPL;  // first row of this lane group
   const int i = (lane / IB) % NC, jc = lane % IB, bofs = lane / CPB;
   // value loads first: their HBM latency overlaps the x staging
-  Ch v[UNR];
-  int nb = 0;
-  if (own) {
-    int64_t rs;
-    st_row<DS>(g, row, rs, nb);
-    const Ch *vbase = reinterpret_cast<const Ch *>(val + rs * NC * NC + i * NC + jc * J);
+  Ch v[RPL][UNR];
+  int nb[RPL];
 #pragma unroll
-    for (int it = 0; it < UNR; it++) {
-      const int b = bofs + it * BPI;
-      if (b < nb) {
-        if constexpr (sizeof(T) == 8) v[it] = __builtin_nontemporal_load(vbase + (int64_t)b * CPB);
-        else v[it] = vbase[(int64_t)b * CPB];
+  for (int r = 0; r < RPL; r++) {
+    nb[r] = 0;
+    if (xr0 + r < n1) {
+      int64_t rs;
+      st_row<DS>(g, line * n1 + xr0 + r, rs, nb[r]);
+      const Ch *vbase = reinterpret_cast<const Ch *>(val + rs * NC * NC + i * NC + jc * J);
+#pragma unroll
+      for (int it = 0; it < UNR; it++) {
+        const int b = bofs + it * BPI;
+        if (b < nb[r]) {
+          if constexpr (sizeof(T) == 8) v[r][it] = __builtin_nontemporal_load(vbase + (int64_t)b * CPB);
+          else v[r][it] = vbase[(int64_t)b * CPB];
+        }
       }
     }
   }
@@ -329,59 +335,69 @@ __device__ __forceinline__ void spmv_tile_lds(int64_t tile, const Stencil &g, co
     xs[e] = *reinterpret_cast<const Ch *>(x + col * NC + c * J);
   }
   __syncthreads();
-  cx<T> acc = mk<cx<T>>(0, 0);
-  if (own) {
-    // LDS slot of each sorted neighbour along axis 1 (inside the tile) and axis 2
-    int lxk[3], lyk[3];
+  // LDS slot of each sorted neighbour along axis 2 (shared by the workgroup)
+  int lyk[3];
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-      int d = nb_coord(xr, n1, k) - (x0 - 1);
-      d += d < 0 ? n1 : 0;
-      d -= d >= n1 ? n1 : 0;
-      lxk[k] = d;
-      int dy = 0;
-      if (DS == 2) {
-        dy = nb_coord(yy, n2, k) - (yy - 1);
-        dy += dy < 0 ? n2 : 0;
-        dy -= dy >= n2 ? n2 : 0;
-      }
-      lyk[k] = dy;
+  for (int k = 0; k < 3; k++) {
+    int dy = 0;
+    if (DS == 2) {
+      dy = nb_coord(yy, n2, k) - (yy - 1);
+      dy += dy < 0 ? n2 : 0;
+      dy -= dy >= n2 ? n2 : 0;
     }
-#pragma unroll
-    for (int it = 0; it < UNR; it++) {
-      const int b = bofs + it * BPI;
-      if (b < nb) {
-        const int kt = b / P, rem = b - kt * P;
-        const int ky = DS == 2 ? rem / 3 : 0, kx = rem - ky * 3;
-        const int lx = kx == 0 ? lxk[0] : (kx == 1 ? lxk[1] : lxk[2]);
-        const int ly = ky == 0 ? lyk[0] : (ky == 1 ? lyk[1] : lyk[2]);
-        acc = chunk_mac<T>(acc, v[it], xs[((kt * NY + ly) * TW + lx) * IB + jc]);
-      }
-    }
+    lyk[k] = dy;
   }
 #pragma unroll
-  for (int off = 1; off < G; off <<= 1) {
-    if (off & IMASK) continue;
-    acc.x += __shfl_xor(acc.x, off, 64);
-    acc.y += __shfl_xor(acc.y, off, 64);
-  }
-  if (own && lane == i * IB) {
-    const int64_t o = row * NC + i;
-    if (RESID) {
-      cx<T> bb = bvec[o];
-      y[o] = mk<cx<T>>(bb.x - acc.x, bb.y - acc.y);
-    } else {
-      y[o] = mk<cx<T>>(alpha * acc.x, alpha * acc.y);
+  for (int r = 0; r < RPL; r++) {
+    const int xr = xr0 + r;
+    const bool own = xr < n1;
+    cx<T> acc = mk<cx<T>>(0, 0);
+    if (own) {
+      // LDS slot of each sorted neighbour along axis 1 (inside the tile)
+      int lxk[3];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        int d = nb_coord(xr, n1, k) - (x0 - 1);
+        d += d < 0 ? n1 : 0;
+        d -= d >= n1 ? n1 : 0;
+        lxk[k] = d;
+      }
+#pragma unroll
+      for (int it = 0; it < UNR; it++) {
+        const int b = bofs + it * BPI;
+        if (b < nb[r]) {
+          const int kt = b / P, rem = b - kt * P;
+          const int ky = DS == 2 ? rem / 3 : 0, kx = rem - ky * 3;
+          const int lx = kx == 0 ? lxk[0] : (kx == 1 ? lxk[1] : lxk[2]);
+          const int ly = ky == 0 ? lyk[0] : (ky == 1 ? lyk[1] : lyk[2]);
+          acc = chunk_mac<T>(acc, v[r][it], xs[((kt * NY + ly) * TW + lx) * IB + jc]);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+      if (off & IMASK) continue;
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (own && lane == i * IB) {
+      const int64_t o = (line * n1 + xr) * NC + i;
+      if (RESID) {
+        cx<T> bb = bvec[o];
+        y[o] = mk<cx<T>>(bb.x - acc.x, bb.y - acc.y);
+      } else {
+        y[o] = mk<cx<T>>(alpha * acc.x, alpha * acc.y);
+      }
     }
   }
 }
 
-template <typename T, int DS, int G, bool RESID>
+template <typename T, int DS, int G, int RPL, bool RESID>
 __global__ __launch_bounds__(256) void spmv_lds_kernel(int64_t ntiles, Stencil g, const cx<T> *__restrict__ val,
                                                        const cx<T> *__restrict__ x,
                                                        const cx<T> *__restrict__ bvec,
                                                        cx<T> *__restrict__ y, T alpha) {
-  spmv_tile_lds<T, DS, G, RESID>(xcd_tile(blockIdx.x, ntiles), g, val, x, bvec, y, alpha);
+  spmv_tile_lds<T, DS, G, RPL, RESID>(xcd_tile(blockIdx.x, ntiles), g, val, x, bvec, y, alpha);
 }
 
 template <typename T, int NC, int DS, int G, bool RESID>
@@ -440,8 +456,9 @@ inline hipError_t launch_spmv_st(const dirac_st_bsr *A, const void *val, const v
   if (A->nc == 4)
     return launch_spmv<T>(A->nc, A->nrows, A->row_ptr, A->col_idx, val, x, bvec, y, alpha, resid, st);
   const Stencil g = make_stencil(&A->prob);
+  constexpr int RPL = 2;
   auto go = [&](auto kern, int G) {
-    const int64_t ntiles = st_tiles(g, 256 / G);
+    const int64_t ntiles = st_tiles(g, 256 / G * RPL);
     const int tk = kt_start(resid ? DIRAC_ST_TIMED_RESID64
                                   : (sizeof(T) == 8 ? DIRAC_ST_TIMED_SPMV64 : DIRAC_ST_TIMED_SPMV32), st);
     kern<<<(unsigned)ntiles, 256, 0, st>>>(ntiles, g, (const cx<T> *)val, (const cx<T> *)x,
@@ -449,10 +466,10 @@ inline hipError_t launch_spmv_st(const dirac_st_bsr *A, const void *val, const v
     kt_stop(tk, st);
     return hipGetLastError();
   };
-  constexpr int G2 = sizeof(T) == 8 ? 32 : 16;
+  constexpr int G2 = sizeof(T) == 8 ? 16 : 8;
   if (g.d == 1)
-    return resid ? go(spmv_lds_kernel<T, 1, G2, true>, G2) : go(spmv_lds_kernel<T, 1, G2, false>, G2);
-  return resid ? go(spmv_lds_kernel<T, 2, G2, true>, G2) : go(spmv_lds_kernel<T, 2, G2, false>, G2);
+    return resid ? go(spmv_lds_kernel<T, 1, G2, RPL, true>, G2) : go(spmv_lds_kernel<T, 1, G2, RPL, false>, G2);
+  return resid ? go(spmv_lds_kernel<T, 2, G2, RPL, true>, G2) : go(spmv_lds_kernel<T, 2, G2, RPL, false>, G2);
 }
 
 }  // namespace dst
