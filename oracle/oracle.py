@@ -371,3 +371,47 @@ def charge(p: Problem, psi0: np.ndarray, x: np.ndarray) -> np.ndarray:
     vol = float(np.prod([p.len[a] / p.n[a] for a in range(1, p.d + 1)]))
     allv = np.concatenate([psi0, x]).reshape(p.n[0] + 1, S, p.nc)
     return vol * np.sum(np.abs(allv) ** 2, axis=(1, 2))
+
+
+def slice_moments(p: Problem, psi0: np.ndarray, x: np.ndarray, x_split: float) -> np.ndarray:
+    """Per time node tau = 0..n_t, trapezoid sums over space (on the periodic
+    uniform mesh: nodal sums times the cell volume) of
+      [ |psi|^2,  |psi|^2 where x_1 > x_split,  x_1 |psi|^2, ..., x_d |psi|^2 ]
+    with node coordinates x_a = i_a h_a.  Column 0 is the charge of Sec. 4.1,
+    columns 2.. the numerators of <x(t)> (Sec. 4.2), columns 1 and 0 - 1 the
+    numerators of T and R (Sec. 4.3, eq. (klein:coeffs)).  Shape [n_t + 1, 2 + d]."""
+    d = p.d
+    ns = [p.n[a] for a in range(1, d + 1)]
+    S = int(np.prod(ns))
+    vol = float(np.prod([p.len[a] / p.n[a] for a in range(1, d + 1)]))
+    allv = np.concatenate([psi0, x]).reshape(p.n[0] + 1, S, p.nc)
+    dens = np.sum(np.abs(allv) ** 2, axis=2)  # [tau][s]
+    idx = np.arange(S)
+    coords = []
+    for a in range(d):
+        coords.append((idx % ns[a]) * (p.len[a + 1] / ns[a]))
+        idx = idx // ns[a]
+    out = np.empty((p.n[0] + 1, 2 + d))
+    out[:, 0] = vol * dens.sum(1)
+    out[:, 1] = vol * dens[:, coords[0] > x_split].sum(1)
+    for a in range(d):
+        out[:, 2 + a] = vol * (dens * coords[a][None, :]).sum(1)
+    return out
+
+
+def free_evolution_1p1(p: Problem, psi0: np.ndarray, t: float) -> np.ndarray:
+    """Exact 1+1 free Dirac evolution on the periodic interval (H = sigma_1 k +
+    sigma_3 m, the Hamiltonian of the App. A gamma pair, App. B) of the
+    trigonometric interpolant of the nodal psi0: every Fourier mode k moves by
+    exp(-i H(k) t) = cos(E t) - i sin(E t) H(k) / E, E = sqrt(k^2 + m^2).  The
+    reference for the Zitterbewegung of Sec. 4.2.  Returns nodal values [n_1][2]."""
+    assert p.d == 1 and p.vkind == 0
+    nx, L, m = p.n[1], p.len[1], p.m
+    u = np.asarray(psi0, np.complex128).reshape(nx, 2)
+    k = 2 * np.pi * np.fft.fftfreq(nx, d=L / nx)
+    a, b = np.fft.fft(u[:, 0]), np.fft.fft(u[:, 1])
+    E = np.sqrt(k * k + m * m)
+    c, s = np.cos(E * t), np.sin(E * t) / E
+    na = c * a - 1j * s * (m * a + k * b)
+    nb = c * b - 1j * s * (k * a - m * b)
+    return np.stack([np.fft.ifft(na), np.fft.ifft(nb)], 1)

@@ -627,3 +627,75 @@ def test_bicgstab_exact_preconditioner_one_iteration():
     assert info["converged"] and info["iters"] == 1
     xd = np.linalg.solve(A.dense(), b)
     assert np.linalg.norm(x - xd) <= 1e-11 * np.linalg.norm(xd)
+
+
+# ------------------------------------------------------ physics diagnostics
+def test_slice_moments_definitions():
+    """Charge column equals the Sec. 4.1 charge; a density that is uniform in
+    space has first moment (mean node coordinate) x charge and a split column
+    equal to the fraction of nodes past the split; rolling a compact packet by
+    one node moves its first moment by h x charge."""
+    spec = IN.Spec(d=2, n=[3, 20, 6], lens=[1.0, 2.0, 1.5])
+    p = as_problem(spec)
+    S = 20 * 6
+    rng = np.random.default_rng(8)
+    psi0 = rng.standard_normal(S * 2) + 1j * rng.standard_normal(S * 2)
+    x = rng.standard_normal(3 * S * 2) + 1j * rng.standard_normal(3 * S * 2)
+    mom = O.slice_moments(p, psi0, x, 0.7)
+    assert np.allclose(mom[:, 0], O.charge(p, psi0, x), rtol=1e-14)
+    # uniform |psi|^2 = 1 on every node
+    u0 = np.full(S * 2, 1 / np.sqrt(2), np.complex128)
+    uu = np.tile(u0, 3)
+    m2 = O.slice_moments(p, u0, uu, 0.7)
+    vol = (2.0 / 20) * (1.5 / 6)
+    assert np.allclose(m2[:, 0], vol * S)
+    assert np.allclose(m2[:, 1], vol * S * np.sum(np.arange(20) * 0.1 > 0.7) / 20)
+    assert np.allclose(m2[:, 2], vol * S * np.mean(np.arange(20) * 0.1))
+    assert np.allclose(m2[:, 3], vol * S * np.mean(np.arange(6) * 0.25))
+    # compact packet rolled by one node along axis 1
+    g = np.zeros((6, 20, 2), np.complex128)
+    g[2:4, 5:9, :] = rng.standard_normal((2, 4, 2))
+    g2 = np.roll(g, 1, axis=1)
+    a = O.slice_moments(p, g.ravel(), np.tile(g.ravel(), 3), 0.7)
+    b = O.slice_moments(p, g2.ravel(), np.tile(g2.ravel(), 3), 0.7)
+    assert np.allclose(b[:, 2] - a[:, 2], 0.1 * a[:, 0])
+
+
+def test_free_evolution_is_exact_for_a_plane_wave():
+    """On a plane wave u_+(k) e^{ikx} (App. B) the Fourier evolution is the
+    closed form u_+ e^{i(kx - E t)}."""
+    spec = IN.Spec(d=1, n=[4, 32], lens=[1.0, 2.0])
+    p = as_problem(spec)
+    k = 2 * np.pi * 3 / 2.0
+    xs = np.arange(32) * 2.0 / 32
+    u = O.plane_wave_spinor(k)
+    psi0 = np.exp(1j * k * xs)[:, None] * u
+    E = np.sqrt(k * k + 1)
+    got = O.free_evolution_1p1(p, psi0.ravel(), 0.37)
+    assert np.allclose(got, psi0 * np.exp(-1j * E * 0.37), atol=1e-13)
+
+
+def test_zitterbewegung_converges_to_free_evolution():
+    """Sec. 4.2: the packet of the paper (width e^{-x^2/16}, spinor (1,1))
+    centred in a periodic box of 40; <x(t)> of the finite-element solution
+    converges at second order to that of the exact free evolution (error ratio
+    4 under halving both steps), over about two Zitterbewegung periods."""
+    Lx, T = 40.0, 6.0
+    errs = []
+    for nx, nt in ((128, 64), (256, 128)):
+        p = O.problem(1, [nt, nx], [T, Lx], 1.0, 0, 0.0, 0.5, 1.0)
+        xs = np.arange(nx) * Lx / nx
+        psi0 = ((1 / (32 * np.pi)) ** 0.25 * np.exp(-(xs - 20) ** 2 / 16))[:, None] * np.array([1, 1])
+        A = O.Matrix(p)
+        sol, info = A.gmres(A.rhs(psi0.ravel()), restart=10, max_it=20, rtol=1e-12, pc="spectral", vbar=0.0)
+        assert info["converged"]
+        mom = O.slice_moments(p, psi0.ravel(), sol, Lx / 2)
+        xm = mom[1:, 2] / mom[1:, 0]
+        ex = []
+        for tau in range(1, nt + 1):
+            e = O.free_evolution_1p1(p, psi0.ravel(), tau * T / nt)
+            dens = np.sum(np.abs(e) ** 2, axis=1)
+            ex.append(np.sum(dens * xs) / np.sum(dens))
+        errs.append(np.abs(xm - np.array(ex)).max())
+    assert 3.7 < errs[0] / errs[1] < 4.3, errs
+    assert errs[1] < 5e-4
