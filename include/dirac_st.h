@@ -323,6 +323,19 @@ size_t dirac_st_bicgstab_workspace_bytes(const dirac_st_bsr *A, const dirac_st_o
 int dirac_st_bicgstab(const dirac_st_bsr *A, const void *b, void *x, const dirac_st_opts *opts,
                       void *work, size_t work_bytes, dirac_st_stats *stats, void *stream);
 
+/* Per-time-slice diagnostics of a solution (trapezoid sums on the periodic
+ * uniform mesh: nodal sums times the cell volume), for tau = 0..n_t (tau = 0
+ * is psi0): out[tau][0] = int |psi|^2 (the charge monitored in Sec. 4.1),
+ * out[tau][1] = the same over x_1 > x_split (the transmitted part of
+ * Sec. 4.3, eq. (klein:coeffs); R's numerator is column 0 minus column 1),
+ * out[tau][2 + a] = int x_{a+1} |psi|^2 with node coordinates i h (the
+ * numerator of <x(t)> of Sec. 4.2).  psi0: device [S][nc] complex128;
+ * x: device [nrows][nc] complex128 (a solution); out: device, (n_t + 1) x
+ * (2 + d) doubles, row-major.  Deterministic (fixed summation order).
+ * Enqueues on `stream`. */
+int dirac_st_slice_moments(const dirac_st_problem *p, const void *psi0, const void *x, double x_split,
+                           double *out, void *stream);
+
 /* Host.  Generalised eigen-decomposition of the Galerkin time pencil used by
  * DIRAC_ST_PC_LINE: the n_t x n_t factors of the t = 1..n_t rows and columns
  * (Sec. 2.1 weak form with the t = 0 node moved to the right-hand side; App. A

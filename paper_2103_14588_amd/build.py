@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdirac_st.so")
-SOURCES = ["api_common.hip", "assemble.hip", "krylov.hip", "cnn.hip", "batched.hip", "time_eigen.hip", "bicgstab.hip"]
+SOURCES = ["api_common.hip", "assemble.hip", "krylov.hip", "cnn.hip", "batched.hip", "time_eigen.hip", "bicgstab.hip", "diag.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -72,6 +72,7 @@ _lib.dirac_st_gmres.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, 
 _lib.dirac_st_nn_param_count.restype = C.c_size_t
 _lib.dirac_st_spmv_mf.argtypes = [C.POINTER(Problem), _i32, _vp, _vp, _vp]
 _lib.dirac_st_rhs_mf.argtypes = [C.POINTER(Problem), _vp, _vp, _vp]
+_lib.dirac_st_slice_moments.argtypes = [C.POINTER(Problem), _vp, _vp, C.c_double, _vp, _vp]
 _lib.dirac_st_bicgstab_workspace_bytes.argtypes = [C.POINTER(BSR), C.POINTER(Opts)]
 _lib.dirac_st_bicgstab_workspace_bytes.restype = C.c_size_t
 _lib.dirac_st_bicgstab.argtypes = [C.POINTER(BSR), _vp, _vp, C.POINTER(Opts), _vp, C.c_size_t,
@@ -112,7 +113,8 @@ EXPORTS = ["dirac_st_last_error", "dirac_st_sizes", "dirac_st_assemble", "dirac_
            "dirac_st_spmv_batched_workspace_bytes", "dirac_st_spmv_batched",
            "dirac_st_batched_set_lanes", "dirac_st_batched_lanes", "dirac_st_time_eigen",
            "dirac_st_timing", "dirac_st_timing_read", "dirac_st_bicgstab_workspace_bytes",
-           "dirac_st_bicgstab", "dirac_st_spmv_mf", "dirac_st_rhs_mf"]
+           "dirac_st_bicgstab", "dirac_st_spmv_mf", "dirac_st_rhs_mf",
+           "dirac_st_slice_moments"]
 
 
 class DiracError(RuntimeError):
@@ -252,6 +254,15 @@ def rhs_mf(spec, psi0: torch.Tensor, b=None):
         b = torch.empty(nrows * spec.nc, dtype=torch.complex128, device=psi0.device)
     _check(_lib.dirac_st_rhs_mf(C.byref(prob), _ptr(psi0), _ptr(b), _stream()))
     return b
+
+
+def slice_moments(spec, psi0: torch.Tensor, x: torch.Tensor, x_split: float) -> torch.Tensor:
+    """dirac_st_slice_moments: [n_t + 1, 2 + d] float64 on the device (charge,
+    charge past x_split, first moments per axis)."""
+    prob = make_problem(spec)
+    out = torch.empty((spec.n[0] + 1, 2 + spec.d), dtype=torch.float64, device=x.device)
+    _check(_lib.dirac_st_slice_moments(C.byref(prob), _ptr(psi0), _ptr(x), float(x_split), _ptr(out), _stream()))
+    return out
 
 
 def problem_operator(spec) -> Operator:
