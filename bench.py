@@ -265,9 +265,9 @@ def batch_bench(args):
     y32 = [torch.empty_like(v) for v in v32]
     nbytes = sum(spmv_bytes(op, 8) for op in ops)
     swork = torch.empty(D.spmv_batched_workspace_bytes(ops), dtype=torch.uint8, device="cuda")
-    for g in (4, 8, 16, 32):
+    for g in (1, 4, 8, 16, 32):  # 1: the x-staged line-tile kernel
         ms = time_launches(lambda: D.spmv_batched(ops, v32, y32, lanes=g, work=swork), args.kernel_reps, torch)
-        spmv[str(g)] = {"ms": round(ms, 4), "GBps": round(nbytes / ms / 1e6, 1)}
+        spmv["lds_tile" if g == 1 else str(g)] = {"ms": round(ms, 4), "GBps": round(nbytes / ms / 1e6, 1)}
     it = np.array([i["iters"] for i in infos])
     print(json.dumps({
         "workload": "64 Klein-step 2+1D systems, n^3 with n ~ U{32..96}, V0 ~ U[0,3] (seed 0): assemble all + "

@@ -417,8 +417,10 @@ size_t dirac_st_spmv_batched_workspace_bytes(int32_t nsys, const dirac_st_bsr *c
  * must come from dirac_st_assemble).  A, x, y:
  * host arrays of nsys pointers; x[i], y[i] device vectors of complex128
  * (prec 64, val64) or complex64 (prec 32, val32).  lanes: lanes per block row,
- * 4, 8, 16 or 32 for nc = 2; 64 (or 32 at prec 32) for nc = 4.  Enqueues only
- * (the small descriptor copy is synchronous). */
+ * 4, 8, 16 or 32 for nc = 2, or 1 for the kernel that stages x in LDS per
+ * tile of 32 consecutive rows of one line of axis 1 (16 lanes per complex128
+ * row serving two rows, 8 per complex64 row); 64 (or 32 at prec 32) for
+ * nc = 4.  Enqueues only (the small descriptor copy is synchronous). */
 int dirac_st_spmv_batched(int32_t nsys, const dirac_st_bsr *const *A, int32_t prec, const void *const *x,
                           void *const *y, int32_t lanes, void *work, size_t work_bytes, void *stream);
 

@@ -32,6 +32,12 @@
 
 namespace dst {
 
+// lane code of the x-staged line-tile SpMV (2x2 blocks) and its rows per
+// workgroup (see g_spmv); codes 4..64 are lanes per block row of the gather
+// kernels
+constexpr int kLdsLanes = 1;
+constexpr int kLdsRows = 32;
+
 struct BSys {
   const int32_t *rp, *ci;
   const void *val64, *val32, *bj64, *bj32;
@@ -94,27 +100,45 @@ __global__ __launch_bounds__(256) void g_fill_tab(const int64_t *__restrict__ of
 
 // ------------------------------------------------------------ grouped kernels
 // mode 0: V_{j+1} = A Z_j (working precision); mode 1: r64 = b - A x (FP64)
+// G = kLdsLanes selects the x-staged line-tile kernel (2x2 blocks): 16 lanes
+// per complex128 row serving 2 rows, 8 lanes per complex64 row serving 1 row,
+// kLdsRows rows per workgroup in both precisions.
 template <typename T, int NC, int G, int MODE>
 __global__ __launch_bounds__(256) void g_spmv(const BSys *__restrict__ S, WorkList L, int j) {
   int64_t tile;
   const BSys &s = S[find_sys(L, tile)];
-  if (MODE == 0) {
-    const cx<T> *z = (const cx<T> *)s.Z + (int64_t)j * s.ldv;
-    cx<T> *w = (cx<T> *)s.V + (int64_t)(j + 1) * s.ldv;
-    const cx<T> *val = (const cx<T> *)(sizeof(T) == 8 ? s.val64 : s.val32);
-    if constexpr (NC == 2) {
-      if (s.st.d == 1) spmv_tile_st<T, 2, 1, G, false>(tile, s.nrows, s.st, val, z, nullptr, w, (T)1);
-      else spmv_tile_st<T, 2, 2, G, false>(tile, s.nrows, s.st, val, z, nullptr, w, (T)1);
+  if constexpr (NC == 2 && G == kLdsLanes) {
+    constexpr int GL = sizeof(T) == 8 ? 16 : 8, RPL = kLdsRows * GL / 256;
+    if (MODE == 0) {
+      const cx<T> *z = (const cx<T> *)s.Z + (int64_t)j * s.ldv;
+      cx<T> *w = (cx<T> *)s.V + (int64_t)(j + 1) * s.ldv;
+      const cx<T> *val = (const cx<T> *)(sizeof(T) == 8 ? s.val64 : s.val32);
+      if (s.st.d == 1) spmv_tile_lds<T, 1, GL, RPL, false>(tile, s.st, val, z, nullptr, w, (T)1);
+      else spmv_tile_lds<T, 2, GL, RPL, false>(tile, s.st, val, z, nullptr, w, (T)1);
     } else {
-      spmv_tile<T, NC, G, false>(tile, s.nrows, s.rp, s.ci, val, z, nullptr, w, (T)1);
+      const double2 *val = (const double2 *)s.val64;
+      if (s.st.d == 1) spmv_tile_lds<double, 1, 16, 2, true>(tile, s.st, val, s.x, s.b, s.r64, 1.0);
+      else spmv_tile_lds<double, 2, 16, 2, true>(tile, s.st, val, s.x, s.b, s.r64, 1.0);
     }
   } else {
-    const double2 *val = (const double2 *)s.val64;
-    if constexpr (NC == 2) {
-      if (s.st.d == 1) spmv_tile_st<double, 2, 1, G, true>(tile, s.nrows, s.st, val, s.x, s.b, s.r64, 1.0);
-      else spmv_tile_st<double, 2, 2, G, true>(tile, s.nrows, s.st, val, s.x, s.b, s.r64, 1.0);
+    if (MODE == 0) {
+      const cx<T> *z = (const cx<T> *)s.Z + (int64_t)j * s.ldv;
+      cx<T> *w = (cx<T> *)s.V + (int64_t)(j + 1) * s.ldv;
+      const cx<T> *val = (const cx<T> *)(sizeof(T) == 8 ? s.val64 : s.val32);
+      if constexpr (NC == 2) {
+        if (s.st.d == 1) spmv_tile_st<T, 2, 1, G, false>(tile, s.nrows, s.st, val, z, nullptr, w, (T)1);
+        else spmv_tile_st<T, 2, 2, G, false>(tile, s.nrows, s.st, val, z, nullptr, w, (T)1);
+      } else {
+        spmv_tile<T, NC, G, false>(tile, s.nrows, s.rp, s.ci, val, z, nullptr, w, (T)1);
+      }
     } else {
-      spmv_tile<double, NC, G, true>(tile, s.nrows, s.rp, s.ci, val, s.x, s.b, s.r64, 1.0);
+      const double2 *val = (const double2 *)s.val64;
+      if constexpr (NC == 2) {
+        if (s.st.d == 1) spmv_tile_st<double, 2, 1, G, true>(tile, s.nrows, s.st, val, s.x, s.b, s.r64, 1.0);
+        else spmv_tile_st<double, 2, 2, G, true>(tile, s.nrows, s.st, val, s.x, s.b, s.r64, 1.0);
+      } else {
+        spmv_tile<double, NC, G, true>(tile, s.nrows, s.rp, s.ci, val, s.x, s.b, s.r64, 1.0);
+      }
     }
   }
 }
@@ -362,6 +386,20 @@ struct BatchLayout {
 // fewest block rows one SpMV workgroup may cover (largest lane count)
 static int64_t rows_per_wg_min(int nc) { return nc == 2 ? 256 / 32 : 256 / 64; }
 
+// SpMV workgroups of one system for lane count g (kLdsLanes: line tiles)
+static int64_t spmv_wgs(const BSys &q, int g) {
+  if (g == kLdsLanes) return st_tiles(q.st, kLdsRows);
+  const int64_t rw = 256 / g;
+  return (q.nrows + rw - 1) / rw;
+}
+
+// table capacity for any lane count of this operator
+static int64_t spmv_wgs_cap(const dirac_st_bsr *A) {
+  int64_t c = (A->nrows + rows_per_wg_min(A->nc) - 1) / rows_per_wg_min(A->nc);
+  if (A->nc == 2) c = std::max(c, st_tiles(make_stencil(&A->prob), kLdsRows));
+  return c;
+}
+
 static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const dirac_st_opts *o) {
   BatchLayout L;
   const size_t cs = o->precision == 32 ? 8 : 16;
@@ -392,7 +430,7 @@ static BatchLayout batch_layout(int nsys, const dirac_st_bsr *const *A, const di
   L.cap_vec = 0;
   L.cap_lines = 0;
   for (int i = 0; i < nsys; i++) {
-    L.cap_rows += (A[i]->nrows + rows_per_wg_min(A[i]->nc) - 1) / rows_per_wg_min(A[i]->nc);
+    L.cap_rows += spmv_wgs_cap(A[i]);
     L.cap_vec += L.nblk[i];
     if (line_kind(o->pc)) L.cap_lines += (line_layout(&A[i]->prob, o->precision, pc_slabs(o)).lines + 63) / 64;
   }
@@ -434,12 +472,11 @@ struct Lists {
     const size_t c1 = (size_t)cap + 1;
     host.assign(kListArrays * c1, 0);
     int64_t *ha = host.data(), *hw = ha + c1, *hr = hw + c1, *hv = hr + c1, *hp = hv + c1;
-    const int64_t rw = 256 / g, rr = 256 / gres;
     for (int a = 0; a < na; a++) {
       const BSys &q = hs[act[a]];
       ha[a] = act[a];
-      hw[a + 1] = hw[a] + (q.nrows + rw - 1) / rw;
-      hr[a + 1] = hr[a] + (q.nrows + rr - 1) / rr;
+      hw[a + 1] = hw[a] + spmv_wgs(q, g);
+      hr[a + 1] = hr[a] + spmv_wgs(q, gres);
       hv[a + 1] = hv[a] + q.nblk;
       for (int k = 0; k < 4; k++) hp[k * c1 + a + 1] = hp[k * c1 + a] + q.lt[k];
     }
@@ -482,7 +519,8 @@ static hipError_t launch_g_spmv(int G, const BSys *S, const WorkList &L, unsigne
                                 hipStream_t s) {
   if (nwg == 0) return hipSuccess;
   if (NC == 2) {
-    if (G == 4) g_spmv<T, 2, 4, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+    if (G == kLdsLanes) g_spmv<T, 2, kLdsLanes, MODE><<<nwg, 256, 0, s>>>(S, L, j);
+    else if (G == 4) g_spmv<T, 2, 4, MODE><<<nwg, 256, 0, s>>>(S, L, j);
     else if (G == 8) g_spmv<T, 2, 8, MODE><<<nwg, 256, 0, s>>>(S, L, j);
     else if (G == 32) g_spmv<T, 2, 32, MODE><<<nwg, 256, 0, s>>>(S, L, j);
     else g_spmv<T, 2, 16, MODE><<<nwg, 256, 0, s>>>(S, L, j);
@@ -510,7 +548,7 @@ static hipError_t launch_g_cgs(int mk, const BSys *S, const WorkList &L, unsigne
 
 // lanes per block row the SpMV may use, for (block size, precision)
 static std::vector<int> lane_candidates(int nc, int prec) {
-  if (nc == 2) return std::vector<int>{4, 8, 16, 32};
+  if (nc == 2) return std::vector<int>{kLdsLanes, 4, 8, 16, 32};
   return prec == 32 ? std::vector<int>{32, 64} : std::vector<int>{64};
 }
 
@@ -995,7 +1033,7 @@ static SpmvBatchLayout spmv_batch_layout(int32_t nsys, const dirac_st_bsr *const
     return r;
   };
   for (int i = 0; i < nsys; i++) {
-    L.cap_rows += (A[i]->nrows + rows_per_wg_min(A[i]->nc) - 1) / rows_per_wg_min(A[i]->nc);
+    L.cap_rows += spmv_wgs_cap(A[i]);
     L.cap_vec += (A[i]->nrows * A[i]->nc + 255) / 256;
   }
   L.desc = take(sizeof(BSys) * nsys);

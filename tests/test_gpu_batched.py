@@ -18,7 +18,7 @@ from paper_2103_14588_amd import inputs as IN
 pytestmark = pytest.mark.gpu
 
 MESHES = [[4, 9, 10], [6, 12, 11], [5, 17, 9], [7, 8, 8], [3, 5, 4]]
-LANES = {(2, 64): [4, 8, 16, 32], (2, 32): [4, 8, 16, 32], (4, 64): [64], (4, 32): [32, 64]}
+LANES = {(2, 64): [1, 4, 8, 16, 32], (2, 32): [1, 4, 8, 16, 32], (4, 64): [64], (4, 32): [32, 64]}
 
 
 @pytest.fixture(scope="module")
