@@ -182,6 +182,39 @@ def slabs_bench(args):
                                   "the time-slab preconditioner, cap %d" % cap, "runs": runs}))
 
 
+def cnn_bench(args):
+    """The learned preconditioner's network on the 2+1D 128^3 grid (the Klein
+    step workload's size): inference (four 3x3x3 convolutions, 4-16-16-16-4
+    channels, bfloat16 on the matrix cores, FP32 accumulation) and one training
+    step (forward, backward data and weights, Adam), timed with HIP events;
+    achieved dense bf16 TFLOP/s against the MI355X peak."""
+    import torch
+    from paper_2103_14588_amd import dirac_st as D
+    from paper_2103_14588_amd import nnpc
+
+    torch.cuda.set_device(0)
+    shape = (128, 128, 128)
+    vox = shape[0] * shape[1] * shape[2]
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(vox * 4, dtype=torch.float32, device="cuda", generator=gen)
+    tgt = torch.randn(vox * 4, dtype=torch.float32, device="cuda", generator=gen)
+    net = D.Net(nnpc.he_init(0))
+    wf = torch.empty(D.nn_workspace_bytes(*shape), dtype=torch.uint8, device="cuda")
+    wt = torch.empty(D.nn_workspace_bytes(*shape, training=True), dtype=torch.uint8, device="cuda")
+    t_fwd = time_launches(lambda: D.nn_forward(net, x, shape, 1.0, wf), args.kernel_reps, torch)
+    t_train = time_launches(lambda: D.nn_train_step(net, x, tgt, shape, 1e-6, work=wt), max(args.kernel_reps // 4, 2),
+                            torch)
+    macs = 27 * (4 * 16 + 16 * 16 + 16 * 16 + 16 * 4)  # per voxel
+    fl = 2.0 * macs * vox
+    peak = 2500.0  # dense bf16 TFLOP/s
+    print(json.dumps({"workload": "network 4-16-16-16-4, 3x3x3 convolutions, 128^3 grid, bfloat16 MFMA",
+                      "forward_ms": round(t_fwd, 4), "forward_gflop": round(fl / 1e9, 2),
+                      "forward_tflops": round(fl / t_fwd / 1e9, 1),
+                      "forward_frac_of_bf16_peak": round(fl / t_fwd / 1e9 / peak, 4),
+                      "train_step_ms": round(t_train, 4),
+                      "train_step_tflops_fwd_plus_2x_bwd": round(3 * fl / t_train / 1e9, 1)}))
+
+
 def batch_bench(args):
     """64 Klein-step systems on uneven meshes n^3, n ~ U{32..96}, V0 ~ U[0, 3m]
     (seeded): one step = assembly of all 64 operators and right-hand sides,
@@ -298,13 +331,14 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--only", choices=["spmv64", "spmv32", "assemble", "copy", "mf64"], default=None,
                     help="launch only this kernel --kernel-reps times (for counter runs)")
-    ap.add_argument("--workload", choices=["packet", "packet3", "plane1", "klein", "batch", "slabs"],
+    ap.add_argument("--workload", choices=["packet", "packet3", "plane1", "klein", "batch", "slabs", "cnn"],
                     default="packet",
                     help="packet: the 2+1D 128^3 packet step (default bench line); packet3: the 3+1D "
                          "32^4 packet; plane1: the 1+1D 64x64 plane wave; klein: the "
                          "learned-preconditioner comparison on the 128^3 Klein step; batch: 64 "
                          "uneven Klein-step systems in one batched solve; slabs: the time-slab "
-                         "preconditioner for 1-32 slabs on the 128^3 packet and Klein step")
+                         "preconditioner for 1-32 slabs on the 128^3 packet and Klein step; cnn: the "
+                         "learned preconditioner's network alone on the 128^3 grid")
     ap.add_argument("--max-it", type=int, default=1500)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -317,6 +351,8 @@ def main():
         return batch_bench(args)
     if args.workload == "slabs":
         return slabs_bench(args)
+    if args.workload == "cnn":
+        return cnn_bench(args)
 
     import numpy as np
     import torch
