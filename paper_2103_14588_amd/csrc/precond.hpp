@@ -262,10 +262,11 @@ static int axis_transform(const SpecGeom &G, const cx<T> *tw, const cx<T> *in, c
   while (stride % ti) ti--;
   const int ntq = (int)(stride / ti);
   const size_t sh = ((size_t)n * ti + n) * sizeof(cx<T>);
-  if ((n & (n - 1)) == 0) {
-    int logn = 0;
+  if ((n & (n - 1)) == 0 && (ti & (ti - 1)) == 0) {
+    int logn = 0, lti = 0;
     while ((1 << logn) < n) logn++;
-    fft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(in, out, n, logn, stride, ti, ntq, sign, sc,
+    while ((1 << lti) < ti) lti++;
+    fft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(in, out, n, logn, stride, lti, ntq, sign, sc,
                                                         tw + G.tw_off[a]);
   } else {
     dft_axis<T><<<(unsigned)(outer * ntq), 256, sh, s>>>(in, out, n, stride, ti, ntq, sign, sc,

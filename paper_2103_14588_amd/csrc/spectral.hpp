@@ -336,46 +336,49 @@ __global__ __launch_bounds__(256) void dft_axis(const cx<T> *in, cx<T> *out, int
 }
 
 // Radix-2 decimation-in-time FFT along one axis of power-of-two length n
-// (same element layout and tiling as dft_axis).  The tile is loaded in
-// bit-reversed order into LDS and log2(n) butterfly stages run in place.
+// (same element layout and tiling as dft_axis, with a power-of-two tile width
+// ti = 2^lti, so every index split is a shift and a mask).  The tile is loaded
+// in bit-reversed order into LDS and log2(n) butterfly stages run in place.
 template <typename T>
 __global__ __launch_bounds__(256) void fft_axis(const cx<T> *in, cx<T> *out, int n, int logn,
-                                                int64_t stride, int ti, int ntile_q, int sign,
+                                                int64_t stride, int lti, int ntile_q, int sign,
                                                 T scale, const cx<T> *__restrict__ tw) {
   using C = cx<T>;
   extern __shared__ unsigned char smem_raw[];
+  const int ti = 1 << lti, qm = ti - 1;
   C *tile = reinterpret_cast<C *>(smem_raw);  // [n][ti]
   C *twl = tile + (size_t)n * ti;             // [n/2]
   const int64_t o = blockIdx.x / ntile_q;
   const int64_t q0 = (int64_t)(blockIdx.x % ntile_q) * ti;
   const int64_t base = o * n * stride + q0;
   for (int t = threadIdx.x; t < n * ti; t += blockDim.x) {
-    const int j = t / ti, q = t % ti;
+    const int j = t >> lti, q = t & qm;
     const int jr = (int)(__brev((unsigned)j) >> (32 - logn));
-    tile[jr * ti + q] = in[base + (int64_t)j * stride + q];
+    tile[(jr << lti) + q] = in[base + (int64_t)j * stride + q];
   }
   for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
     C w = tw[t];
     twl[t] = mk<C>(w.x, sign < 0 ? w.y : -w.y);
   }
   __syncthreads();
-  for (int len = 2, lstep = n / 2; len <= n; len <<= 1, lstep >>= 1) {
-    const int half = len >> 1;
+  for (int lh = 0, lstep = n / 2; lh < logn; lh++, lstep >>= 1) {
+    // stage with butterfly span half = 2^lh
+    const int hm = (1 << lh) - 1;
     for (int t = threadIdx.x; t < (n / 2) * ti; t += blockDim.x) {
-      const int q = t % ti, k = t / ti;
-      const int grp = k / half, pos = k - grp * half;
-      const int i0 = grp * len + pos, i1 = i0 + half;
+      const int q = t & qm, k = t >> lti;
+      const int pos = k & hm;
+      const int i0 = ((k >> lh) << (lh + 1)) + pos, i1 = i0 + (1 << lh);
       const C w = twl[pos * lstep];
-      const C a = tile[i0 * ti + q], b = tile[i1 * ti + q];
+      const C a = tile[(i0 << lti) + q], b = tile[(i1 << lti) + q];
       const C tb = cmul(w, b);
-      tile[i0 * ti + q] = cadd(a, tb);
-      tile[i1 * ti + q] = csub(a, tb);
+      tile[(i0 << lti) + q] = cadd(a, tb);
+      tile[(i1 << lti) + q] = csub(a, tb);
     }
     __syncthreads();
   }
   for (int t = threadIdx.x; t < n * ti; t += blockDim.x) {
-    const int k = t / ti, q = t % ti;
-    const C v = tile[k * ti + q];
+    const int k = t >> lti, q = t & qm;
+    const C v = tile[(k << lti) + q];
     out[base + (int64_t)k * stride + q] = mk<C>(v.x * scale, v.y * scale);
   }
 }
