@@ -5,15 +5,18 @@
 // two spinor components in and out), ReLU between layers, periodic padding in
 // space and zero padding in time.  Activations are channels-last bfloat16
 // [voxel][c]; weights are bfloat16 [tap][cin][cout] (tap = (dt+1)*9 +
-// (dy+1)*3 + (dx+1)); accumulation is FP32 on the matrix cores
-// (v_mfma_f32_16x16x16_bf16); biases, master weights, the loss and Adam are FP32.
+// (dy+1)*3 + (dx+1)); accumulation is FP32 on the matrix cores; biases,
+// master weights, the loss and Adam are FP32.
 //
-// Convolution as an implicit GEMM: for 16 output voxels (one MFMA row tile)
-// and 16 output channels the K dimension runs over (tap, input channel).  A
-// workgroup owns a 4 x 4 x 16 voxel tile (one tau slice per wavefront, one
-// y-row of 16 x per MFMA tile) and stages its halo 6 x 6 x 18 in LDS.
+// Convolution as an implicit GEMM (v_mfma_f32_16x16x32_bf16): for 16 output
+// voxels (one MFMA row tile) and 16 output channels the K dimension runs over
+// (tap, input channel), 32 at a time.  A persistent workgroup walks 4 x 4 x 16
+// voxel tiles (one tau slice per wavefront, one y-row of 16 x per MFMA tile)
+// with the 6 x 6 x 18 halo double-buffered in LDS in a conflict-free
+// chunk-planar layout, and stores through a per-wavefront LDS transpose.
 // Backward data is the same kernel with the taps flipped and cin/cout swapped;
-// backward weights is an MFMA reduction over voxels (K = voxels).
+// backward weights is an MFMA reduction over voxels (K = voxels,
+// v_mfma_f32_16x16x16_bf16).
 #pragma once
 
 #include <cstdint>
@@ -43,136 +46,298 @@ struct Grid3 {
   int64_t V;
 };
 
-// tile index -> origin; halo voxel (a, b, c) -> global voxel index or -1
-__device__ inline void tile_origin(const Grid3 &g, int64_t tile, int &t0, int &y0, int &x0) {
-  const int tx = (int)(tile % g.tiles_x);
-  const int64_t r = tile / g.tiles_x;
-  const int ty = (int)(r % g.tiles_y);
-  const int tt = (int)(r / g.tiles_y);
+// tile index -> origin; halo voxel (a, b, c) -> global voxel index or -1.
+// Tile counts stay far below 2^31 (a grid of 2^31 tiles would need terabytes
+// of activations), so tile arithmetic is 32-bit.
+__device__ inline void tile_origin(const Grid3 &g, int tile, int &t0, int &y0, int &x0) {
+  const int tx = tile % g.tiles_x;
+  const int r = tile / g.tiles_x;
+  const int ty = r % g.tiles_y;
+  const int tt = r / g.tiles_y;
   t0 = tt * TT;
   y0 = ty * TY;
   x0 = tx * TX;
 }
 
+// periodic wrap of a coordinate in [-1, n + 16]: one add, a few subtractions
+// only on axes shorter than the tile
+__device__ inline int wrap_axis(int v, int n) {
+  v += v < 0 ? n : 0;
+  while (v >= n) v -= n;
+  return v;
+}
+
 __device__ inline int64_t halo_voxel(const Grid3 &g, int t0, int y0, int x0, int a, int b, int c) {
   const int t = t0 - 1 + a;
   if (t < 0 || t >= g.nt) return -1;
-  int y = y0 - 1 + b, x = x0 - 1 + c;
-  y = (y % g.ny + g.ny) % g.ny;
-  x = (x % g.nx + g.nx) % g.nx;
+  const int y = wrap_axis(y0 - 1 + b, g.ny), x = wrap_axis(x0 - 1 + c, g.nx);
   return ((int64_t)t * g.ny + y) * g.nx + x;
 }
 
 enum ConvMode { CONV_RELU = 0, CONV_F32 = 1, CONV_BWD = 2 };
 
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+constexpr int kHaloVox = HT * HY * HX;             // 648 halo voxels per tile
+constexpr int kHaloRounds = (kHaloVox + 255) / 256;  // staging rounds of 256 threads
+
+// Halo of one tile, fetched into registers (CIN bf16 per voxel, 0 outside the
+// time range): round u covers halo voxel threadIdx.x + 256 u.  Every lane
+// issues the same loads (an address outside the halo or the time range is
+// replaced by voxel 0 and the data zeroed), so the number of loads in flight
+// is the same on every path and later waits need not drain them; bit u of
+// the returned mask says whether round u's data is real (zeroed on the put).
+template <int CIN>
+__device__ __forceinline__ unsigned halo_fetch(const Grid3 &g, int tile, const uint16_t *__restrict__ in,
+                                               uint4 (&pre)[kHaloRounds][2]) {
+  unsigned okm = 0;
+  int t0, y0, x0;
+  tile_origin(g, tile, t0, y0, x0);
+#pragma unroll
+  for (int u = 0; u < kHaloRounds; u++) {
+    const int hv = threadIdx.x + 256 * u;
+    const int c = hv % HX, b = (hv / HX) % HY, a = hv / (HX * HY);
+    int64_t vox = hv < kHaloVox ? halo_voxel(g, t0, y0, x0, a, b, c) : -1;
+    okm |= vox >= 0 ? 1u << u : 0u;
+    vox = vox >= 0 ? vox : 0;
+    if constexpr (CIN == 16) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(in + vox * 16);
+      pre[u][0] = src[0];
+      pre[u][1] = src[1];
+    } else {
+      const uint2 q = *reinterpret_cast<const uint2 *>(in + vox * 4);
+      pre[u][0] = make_uint4(q.x, q.y, 0, 0);
+    }
+  }
+  return okm;
+}
+
+// LDS halo layout, chunk-planar: for every halo row (a, b) the CIN / 4 chunks
+// of 4 channels (8 bytes) are planes of HX voxels,
+//   element offset (((a HY + b) CIN / 4 + q) HX + c) 4,
+// so 16 lanes reading one chunk of 16 consecutive voxels read 128 contiguous
+// bytes (no bank conflicts) and every operand address is a per-lane base plus
+// a constant.  (For CIN = 4 this is the plain [a][b][c][4] order.)
+template <int CIN>
+__device__ __forceinline__ int halo_off(int a, int b, int q, int c) {
+  return (((a * HY + b) * (CIN / 4) + q) * HX + c) * 4;
+}
+
+template <int CIN>
+__device__ __forceinline__ void halo_put(uint16_t *buf, const uint4 (&pre)[kHaloRounds][2], unsigned okm) {
+#pragma unroll
+  for (int u = 0; u < kHaloRounds; u++) {
+    const int hv = threadIdx.x + 256 * u;
+    if (hv < kHaloVox) {
+      const int c = hv % HX, b = (hv / HX) % HY, a = hv / (HX * HY);
+      const uint4 z = make_uint4(0, 0, 0, 0);
+      const uint4 p0 = (okm >> u) & 1 ? pre[u][0] : z, p1 = (okm >> u) & 1 ? pre[u][1] : z;
+      if constexpr (CIN == 16) {
+        *reinterpret_cast<uint2 *>(buf + halo_off<16>(a, b, 0, c)) = make_uint2(p0.x, p0.y);
+        *reinterpret_cast<uint2 *>(buf + halo_off<16>(a, b, 1, c)) = make_uint2(p0.z, p0.w);
+        *reinterpret_cast<uint2 *>(buf + halo_off<16>(a, b, 2, c)) = make_uint2(p1.x, p1.y);
+        *reinterpret_cast<uint2 *>(buf + halo_off<16>(a, b, 3, c)) = make_uint2(p1.z, p1.w);
+      } else {
+        *reinterpret_cast<uint2 *>(buf + halo_off<4>(a, b, 0, c)) = make_uint2(p0.x, p0.y);
+      }
+    }
+  }
+}
+
+// K = 32 slices of the implicit GEMM (v_mfma_f32_16x16x32_bf16).  Lane group
+// kg = lane / 16 holds the logical k = 8 kg .. 8 kg + 7 of both operands; A
+// and B pair their k-slots the same way, so the sum does not depend on the
+// order the matrix core adds them in.  Logical k of step s, element i:
+//   CIN 16: tap 2 s + i / 4, channel 4 kg + i % 4   (14 steps, tap 27 = 0): the
+//           taps are the same in every lane, so each operand address is one
+//           per-lane base plus a constant offset
+//   CIN 4 : tap 8 s + 2 kg + i / 4, channel i % 4   (4 steps, taps >= 27 = 0)
+template <int CIN>
+struct ConvSteps {
+  static constexpr int N = CIN == 16 ? 14 : 4;
+};
+
+// A operand of step s for output row r.  base = element offset of halo voxel
+// (tl, 0, 0) of the current buffer plus this lane's voxel x = mrow (and, for
+// CIN 16, its channel chunk kg): CIN 16 reads base + a constant per (s, r);
+// CIN 4 spreads taps over the lane groups.
+template <int CIN>
+__device__ __forceinline__ s8v conv_a(const uint16_t *halo, int base, int s, int r, int kg) {
+  typedef short s4 __attribute__((ext_vector_type(4)));
+  auto at = [&](int tap) {
+    const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    return *reinterpret_cast<const s4 *>(halo + base + halo_off<CIN>(1 + dt, r + 1 + dy, 0, 1 + dx));
+  };
+  s4 lo = {0, 0, 0, 0}, hi = lo;
+  if constexpr (CIN == 16) {
+    lo = at(2 * s);
+    if (2 * s + 1 < 27) hi = at(2 * s + 1);
+  } else {
+    const int tap = 8 * s + 2 * kg;
+    if (tap < 27) lo = at(tap);
+    if (tap + 1 < 27) hi = at(tap + 1);
+  }
+  return s8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
 // out = conv(in, W) (+ bias) with the epilogue of MODE:
 //   CONV_RELU: bf16(relu(acc + bias))              -> out16 [V][COUT]
 //   CONV_F32 : acc + bias (FP32)                     -> out32 [V][COUT]
 //   CONV_BWD : bf16(acc) where mask[v][co] > 0, else 0 -> out16 (ReLU adjoint)
+// A workgroup walks its tiles with the halo double-buffered in LDS: the next
+// tile's halo is fetched into registers before the current tile's MFMAs and
+// written to the other buffer after them, one barrier per tile.
 template <int CIN, int COUT, int MODE>
-__global__ __launch_bounds__(256) void conv3d_mfma(Grid3 g, const uint16_t *__restrict__ in,
+// (three wavefronts per SIMD, two for the 16-channel backward pass, whose ReLU
+// masks take 16 more registers)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == CONV_BWD && CIN == 16 ? 2 : 3)))
+void conv3d_mfma(Grid3 g, const uint16_t *__restrict__ in,
                                                    const uint16_t *__restrict__ W,
                                                    const float *__restrict__ bias,
                                                    const uint16_t *__restrict__ mask,
                                                    uint16_t *__restrict__ out16,
                                                    float *__restrict__ out32) {
   static_assert(CIN == 4 || CIN == 16, "cin");
-  static_assert(COUT == 4 || COUT == 16, "cout");
-  constexpr int KSTEPS = CIN == 16 ? 27 : 7;  // MFMAs per output tile
-  __shared__ __attribute__((aligned(16))) uint16_t halo[HT * HY * HX * CIN];
+  static_assert(COUT == 16 || (COUT == 4 && MODE == CONV_F32), "bf16 outputs have 16 channels");
+  constexpr int NS = ConvSteps<CIN>::N;
+  constexpr int HB = kHaloVox * CIN;  // elements per halo buffer
+  __shared__ __attribute__((aligned(16))) uint16_t halo[2 * HB];
+  __shared__ __attribute__((aligned(16))) uint16_t ep[4][256];  // per-wavefront output transpose
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mrow = lane & 15, kg = lane >> 4;
-  // B operands for this lane, all K steps: W[tap][ci][co], co = lane % 16
-  s4v bw[KSTEPS];
+  const int ntiles = g.tiles_t * g.tiles_y * g.tiles_x;
+  int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  // weights W[tap][ci][co] staged in the second halo buffer as Wt[co][tap][ci]
+  // (taps 27.. and channels co >= COUT zero), so each lane reads its B
+  // operands (co = lane % 16) in 8-byte pieces
+  constexpr int WT = 32 * CIN;  // bf16 per co row
+  static_assert(16 * WT <= kHaloVox * CIN, "weights fit one halo buffer");
+  uint16_t *wt = halo + HB;
+  for (int e = threadIdx.x; e < 16 * WT; e += 256) {
+    const int co = e / WT, tap = (e % WT) / CIN, ci = e % CIN;
+    wt[e] = (tap < 27 && co < COUT) ? W[(tap * CIN + ci) * COUT + co] : (uint16_t)0;
+  }
+  uint4 pre[kHaloRounds][2];
+  halo_put<CIN>(halo, pre, halo_fetch<CIN>(g, tile, in, pre));
+  __syncthreads();
+  bf8v bw[NS];
+  {
+    typedef short s4 __attribute__((ext_vector_type(4)));
+    const uint16_t *wr = wt + mrow * WT;
 #pragma unroll
-  for (int s = 0; s < KSTEPS; s++) {
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      int tap, ci;
-      if (CIN == 16) {
-        tap = s;
-        ci = 4 * kg + i;
-      } else {
-        tap = 4 * s + kg;
-        ci = i;
-      }
-      const int co = mrow;
-      short v = 0;
-      if (tap < 27 && co < COUT) v = (short)W[(tap * CIN + ci) * COUT + co];
-      bw[s][i] = v;
+    for (int s = 0; s < NS; s++) {
+      // same k-slots as conv_a: (tap, channel) of elements 0..3 and 4..7
+      const int ta = CIN == 16 ? 2 * s : 8 * s + 2 * kg;
+      const int c0 = CIN == 16 ? 4 * kg : 0;
+      const s4 lo = *reinterpret_cast<const s4 *>(wr + ta * CIN + c0);
+      const s4 hi = *reinterpret_cast<const s4 *>(wr + (ta + 1) * CIN + c0);
+      const s8v v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      bw[s] = __builtin_bit_cast(bf8v, v);
     }
   }
-  const int64_t ntiles = (int64_t)g.tiles_t * g.tiles_y * g.tiles_x;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  __syncthreads();  // every lane holds its weights before halo[1] is refilled
+  // global loads of the epilogue (bias, ReLU mask) are issued before the next
+  // tile's halo fetch: the memory counter is in order, so a wait for a load
+  // issued after the fetch would also wait for the fetch
+  const int co = mrow;
+  float bco = (MODE != CONV_BWD && co < COUT) ? bias[co] : 0.f;
+  asm volatile("" : "+v"(bco));  // wait for it here, not inside the loop
+  const int xv = lane >> 1, half = lane & 1;  // epilogue store: lanes 0..31 own voxel xv, channels 8 half ..
+  for (int cur = 0; tile < ntiles; tile += gridDim.x, cur ^= 1) {
     int t0, y0, x0;
     tile_origin(g, tile, t0, y0, x0);
-    __syncthreads();
-    // stage the halo: CIN bf16 per voxel, zero outside the time range
-    for (int hv = threadIdx.x; hv < HT * HY * HX; hv += 256) {
-      const int c = hv % HX, b = (hv / HX) % HY, a = hv / (HX * HY);
-      const int64_t vox = halo_voxel(g, t0, y0, x0, a, b, c);
-      uint16_t *dst = halo + hv * CIN;
-      if (CIN == 16) {
-        uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
-        if (vox >= 0) {
-          const uint4 *src = reinterpret_cast<const uint4 *>(in + vox * 16);
-          q0 = src[0];
-          q1 = src[1];
-        }
-        reinterpret_cast<uint4 *>(dst)[0] = q0;
-        reinterpret_cast<uint4 *>(dst)[1] = q1;
-      } else {
-        uint2 q = make_uint2(0, 0);
-        if (vox >= 0) q = *reinterpret_cast<const uint2 *>(in + vox * 4);
-        *reinterpret_cast<uint2 *>(dst) = q;
+    const int t = t0 + wave;
+    uint4 mk[TY];
+    if constexpr (MODE == CONV_BWD) {
+#pragma unroll
+      for (int r = 0; r < TY; r++) {
+        mk[r] = make_uint4(0, 0, 0, 0);
+        const int y = y0 + r;
+        if (t < g.nt && y < g.ny && lane < 32 && x0 + xv < g.nx)
+          mk[r] = *reinterpret_cast<const uint4 *>(mask + ((((int64_t)t * g.ny + y) * g.nx + x0 + xv) * 16 + 8 * half));
       }
     }
-    __syncthreads();
+    const int next = tile + (int)gridDim.x;
+    const unsigned okm = halo_fetch<CIN>(g, next < ntiles ? next : tile, in, pre);  // unconditional: fixed load count
     const int tl = wave;  // tau within tile
+    // operand base of this lane in the current buffer, opaque to the
+    // optimiser so that each read is the base plus an immediate offset
+    // (hoisting every (s, r) address out of the tile loop would cost a
+    // register each)
+    int base = cur * HB + halo_off<CIN>(tl, 0, CIN == 16 ? kg : 0, mrow);
+    asm volatile("" : "+v"(base));
+    f4v acc[TY];
+#pragma unroll
+    for (int r = 0; r < TY; r++) acc[r] = {0.f, 0.f, 0.f, 0.f};
+    // A operands one step ahead: the reads of step s + 1 are in flight during
+    // the MFMAs of step s (the scheduling barrier keeps the compiler from
+    // hoisting every step's reads, which would cost registers and occupancy)
+    s8v ac[TY];
+#pragma unroll
+    for (int r = 0; r < TY; r++) ac[r] = conv_a<CIN>(halo, base, 0, r, kg);
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      s8v an[TY];
+      if (s + 1 < NS) {
+#pragma unroll
+        for (int r = 0; r < TY; r++) an[r] = conv_a<CIN>(halo, base, s + 1, r, kg);
+      }
+#pragma unroll
+      for (int r = 0; r < TY; r++)
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, ac[r]), bw[s], acc[r], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (s + 1 < NS) {
+#pragma unroll
+        for (int r = 0; r < TY; r++) ac[r] = an[r];
+      }
+    }
+    // D[m = 4 kg + i][n = lane % 16] is voxel x0 + 4 kg + i, channel co: the
+    // wavefront transposes each 16-voxel row through LDS so that a lane
+    // stores 16 contiguous bytes of one voxel
+    uint16_t *e = ep[wave];
 #pragma unroll
     for (int r = 0; r < TY; r++) {
-      f4v acc = {0.f, 0.f, 0.f, 0.f};
+      const int y = y0 + r;
+      if (t >= g.nt || y >= g.ny) continue;  // uniform over the wavefront
+      const int64_t row = ((int64_t)t * g.ny + y) * g.nx;
+      if constexpr (MODE == CONV_F32) {
+        float *ef = reinterpret_cast<float *>(e);  // [16 voxels][4 channels]
+        if (co < COUT) {
 #pragma unroll
-      for (int s = 0; s < KSTEPS; s++) {
-        int tap, c0;
-        if (CIN == 16) {
-          tap = s;
-          c0 = 4 * kg;
-        } else {
-          tap = 4 * s + kg;
-          c0 = 0;
+          for (int i = 0; i < 4; i++) ef[(4 * kg + i) * 4 + co] = acc[r][i] + bco;
         }
-        s4v a = {0, 0, 0, 0};
-        if (tap < 27) {
-          const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-          const int hv = ((tl + 1 + dt) * HY + (r + 1 + dy)) * HX + (mrow + 1 + dx);
-          a = *reinterpret_cast<const s4v *>(halo + hv * CIN + c0);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[s], acc, 0, 0, 0);
-      }
-      // D[m = 4 kg + i][n = lane % 16]: voxel x = x0 + 4 kg + i, channel co
-      const int co = mrow;
-      const int t = t0 + tl, y = y0 + r;
-      if (co < COUT && t < g.nt && y < g.ny) {
+        if (lane < 16 && x0 + lane < g.nx)
+          *reinterpret_cast<float4 *>(out32 + (row + x0 + lane) * 4) = reinterpret_cast<const float4 *>(ef)[lane];
+      } else {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-          const int x = x0 + 4 * kg + i;
-          if (x >= g.nx) continue;
-          const int64_t vox = ((int64_t)t * g.ny + y) * g.nx + x;
-          float v = acc[i];
-          if (MODE == CONV_RELU) {
-            v += bias[co];
-            // written so that NaN propagates (a broken network must show)
-            out16[vox * COUT + co] = f2bf(v <= 0.f ? 0.f : v);
-          } else if (MODE == CONV_F32) {
-            out32[vox * COUT + co] = v + bias[co];
-          } else {
-            const float mk = bf2f(mask[vox * COUT + co]);
-            out16[vox * COUT + co] = f2bf(mk > 0.f ? v : 0.f);
+          float v = acc[r][i];
+          // written so that NaN propagates (a broken network must show)
+          if (MODE == CONV_RELU) v = (v + bco) <= 0.f ? 0.f : v + bco;
+          e[(4 * kg + i) * 16 + co] = f2bf(v);
+        }
+        if (lane < 32 && x0 + xv < g.nx) {
+          const int64_t o = (row + x0 + xv) * 16 + 8 * half;
+          uint4 q = reinterpret_cast<const uint4 *>(e)[lane];
+          if constexpr (MODE == CONV_BWD) {
+            // ReLU adjoint: keep the gradient where the forward activation was positive
+            const uint4 m = mk[r];
+            // (a bfloat16 is > 0 exactly when its bits lie in (0, 0x7F80]:
+            // positive, +inf included, NaN and -0 excluded)
+            auto pos = [](uint32_t b) { return b - 1u < 0x7F80u; };
+            auto keep = [&](uint32_t gv, uint32_t m) {
+              return (pos(m & 0xFFFFu) ? (gv & 0xFFFFu) : 0u) | (pos(m >> 16) ? (gv & 0xFFFF0000u) : 0u);
+            };
+            q = make_uint4(keep(q.x, m.x), keep(q.y, m.y), keep(q.z, m.z), keep(q.w, m.w));
           }
+          *reinterpret_cast<uint4 *>(out16 + o) = q;
         }
       }
     }
+    if (next < ntiles) halo_put<CIN>(halo + (cur ^ 1) * HB, pre, okm);
+    __syncthreads();
   }
 }
 
@@ -306,14 +471,23 @@ __global__ __launch_bounds__(256) void bias_grad_partial(const uint16_t *__restr
   }
 }
 
-// out[j] = sum_b partial[b][j] (fixed order), j < m
+// out[j] = sum_b partial[b][j], j < m, in a fixed order: a workgroup owns 64
+// consecutive j (one per lane, coalesced rows); wavefront w sums rows
+// w, w + 4, ... and the four sums are added in wavefront order
+constexpr int kReduceCols = 64;
 __global__ __launch_bounds__(256) void reduce_rows(const float *__restrict__ partial, int nb, int m,
                                                    float *__restrict__ out) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= m) return;
+  __shared__ double red[4][kReduceCols];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * kReduceCols + lane;
   double s = 0.0;
-  for (int b = 0; b < nb; b++) s += partial[(int64_t)b * m + j];
-  out[j] = (float)s;
+  if (j < m) {
+#pragma unroll 8
+    for (int b = w; b < nb; b += 4) s += partial[(int64_t)b * m + j];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < m) out[j] = (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 // a0 = bf16(x * s) for complex64 input viewed as [V][4] floats
