@@ -382,6 +382,13 @@ def main():
                           "GBps": nbytes / ms / 1e6}))
         return
     m, rtol = wl.restart, wl.rtol
+    # The timed step's operator: its complex128 GMRES with the spectral
+    # preconditioner reads only the complex128 blocks (with their pattern), so
+    # the step assembles those and not the complex64 copy or the node-block
+    # inverses; the full operator above serves the FP32-IR, block-Jacobi and
+    # BiCGSTAB comparisons and the isolated kernel timings.
+    op64, b64 = D.assemble(spec, psi0, fp32=False, block_jacobi=False)
+    asm64_bytes = op64.bytes() + op64.n * 16 + psi0.numel() * 16
     o32 = D.make_opts(restart=m, max_it=2000, pc="spectral", precision=32, rtol=rtol,
                       inner_rtol=1e-4, vbar=0.0)
     o64 = D.make_opts(restart=m, max_it=2000, pc="spectral", precision=64, rtol=rtol, vbar=0.0)
@@ -389,9 +396,9 @@ def main():
                        dtype=torch.uint8, device="cuda")
 
     def step():
-        D.assemble_into(op, psi0, b)
+        D.assemble_into(op64, psi0, b64)
         x.zero_()
-        _, info = D.gmres(op, b, x, opts=o64, work=work)
+        _, info = D.gmres(op64, b64, x, opts=o64, work=work)
         return info
 
     for _ in range(args.warmup):
@@ -495,8 +502,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": "%s Q1 spacetime Dirac (seed 0); assemble + complex128 GMRES(%d) "
-                               "(spectral PC) to relres %g" % (wl.name, m, rtol),
+        "config": {"workload": "%s Q1 spacetime Dirac (seed 0); assemble (complex128 blocks) + complex128 "
+                               "GMRES(%d) (spectral PC) to relres %g" % (wl.name, m, rtol),
                    "mesh_elements": spec.n, "unknowns": op.n, "blocks": op.nnzb, "restart": m,
                    "rtol": rtol},
         "solve": {
@@ -534,16 +541,19 @@ def main():
              "frac": round(res_bytes / l_res / 1e6 / HBM_PEAK_GBS, 4)},
             "assemble": None if l_asm is None else
             {"bound": "hbm", "avg_launch_ms": round(l_asm, 4), "launches_timed": n_asm,
-             "algorithmic_bytes": asm_bytes, "achieved": round(asm_bytes / l_asm / 1e6, 1),
-             "frac": round(asm_bytes / l_asm / 1e6 / HBM_PEAK_GBS, 4)},
+             "writes": "complex128 blocks, pattern, right-hand side (the step's operator)",
+             "algorithmic_bytes": asm64_bytes, "achieved": round(asm64_bytes / l_asm / 1e6, 1),
+             "frac": round(asm64_bytes / l_asm / 1e6 / HBM_PEAK_GBS, 4)},
             "spmv_matrix_free_c128": {"bound": "hbm", "avg_launch_ms": round(t_mf64, 4),
                                       "algorithmic_bytes": 2 * op.n * 16,
                                       "achieved": round(2 * op.n * 16 / t_mf64 / 1e6, 1),
                                       "frac": round(2 * op.n * 16 / t_mf64 / 1e6 / HBM_PEAK_GBS, 4),
                                       "speedup_vs_stored_blocks": round(t_spmv64 / t_mf64, 2)}},
         "assembly": {"ms": round(t_asm, 4), "bytes_written": asm_bytes,
-                     "GBps": round(asm_bytes / t_asm / 1e6, 1)},
-        "memory_GB": round((op.bytes() + work.numel()) / 1e9, 3),
+                     "GBps": round(asm_bytes / t_asm / 1e6, 1),
+                     "writes": "complex128 and complex64 blocks, pattern, node-block inverses in both "
+                               "precisions, right-hand side (the full operator, isolated launches)"},
+        "memory_GB": round((op.bytes() + op64.bytes() + work.numel()) / 1e9, 3),
     }
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(wl, [x32.cpu().numpy(), x64.cpu().numpy()])

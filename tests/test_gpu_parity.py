@@ -182,6 +182,37 @@ def test_gmres_solution_matches_exact(D, spec, precision):
     assert info["relres"] <= 1e-11
 
 
+@pytest.mark.parametrize("spec", [
+    IN.Spec(d=2, n=[6, 17, 9], lens=[1.0, 0.9, 1.1], vkind=1, v0=2.5, x0=0.5),
+    IN.Spec(d=1, n=[7, 37], lens=[0.8, 1.3]),
+], ids=ids)
+def test_complex128_only_assembly(D, spec):
+    """Assembly without the complex64 copy and the node-block inverses (all a
+    complex128 solve with the spectral or line preconditioner reads): the same
+    pattern, complex128 blocks and right-hand side as the full assembly, bit
+    for bit, also when assembled again into the same arrays; the complex128
+    spectral solve on it lands on the exact discrete solution; a complex64
+    solve and node-block Jacobi are refused on it."""
+    psi0 = rand_c(spec.spatial * spec.nc, 5)
+    full, b_full = D.assemble(spec, dev(psi0))
+    lean, b = D.assemble(spec, dev(psi0), fp32=False, block_jacobi=False)
+    assert lean.val32 is None and lean.bjinv64 is None and lean.bjinv32 is None
+    for _ in range(2):
+        assert torch.equal(lean.row_ptr, full.row_ptr) and torch.equal(lean.col_idx, full.col_idx)
+        assert torch.equal(lean.val64, full.val64) and torch.equal(b, b_full)
+        D.assemble_into(lean, dev(psi0), b)
+    A_or = O.Matrix(oprob(spec))
+    x_ref = np.linalg.solve(A_or.dense(), A_or.rhs(psi0))
+    vbar = 0.5 * spec.v0 if spec.vkind else 0.0
+    x, info = D.gmres(lean, b, restart=20, max_it=2000, rtol=1e-11, pc="spectral", vbar=vbar)
+    assert info["converged"], info
+    assert np.linalg.norm(host(x) - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+    with pytest.raises(D.DiracError):
+        D.gmres(lean, b, restart=5, max_it=5, pc="spectral", precision=32, inner_rtol=1e-4)
+    with pytest.raises(D.DiracError):
+        D.gmres(lean, b, restart=5, max_it=5, pc="bj")
+
+
 def test_gmres_pc_none_and_restart_one(D):
     spec = IN.Spec(d=1, n=[3, 4])
     A_or = O.Matrix(oprob(spec))
