@@ -237,6 +237,11 @@ def batch_bench(args):
         op, b = D.assemble(w.spec, p, block_jacobi=False)
         ops.append(op)
         bs.append(b)
+    # the timed step's operators: its complex128 FGMRES with the line
+    # preconditioner reads only the complex128 blocks, so the step assembles
+    # those (no complex64 copies); the operators above serve the FP32-IR
+    # comparison and the complex64 SpMV measurements
+    ops64 = [D.assemble(w.spec, None, fp32=False, block_jacobi=False)[0] for w in wls]
     xs = [torch.zeros_like(b) for b in bs]
     kw = dict(restart=10, max_it=200, rtol=1e-8, pc="line", inner_rtol=1e-5)
     o32 = D.make_opts(precision=32, **kw)
@@ -245,11 +250,11 @@ def batch_bench(args):
                        dtype=torch.uint8, device="cuda")
 
     def step():
-        for op, p, b in zip(ops, psis, bs):
+        for op, p, b in zip(ops64, psis, bs):
             D.assemble_into(op, p, b)
         for x in xs:
             x.zero_()
-        _, infos, rc = D.fgmres_batched(ops, bs, xs, opts=o64, work=work)
+        _, infos, rc = D.fgmres_batched(ops64, bs, xs, opts=o64, work=work)
         return infos
 
     for _ in range(args.warmup):
@@ -303,8 +308,8 @@ def batch_bench(args):
         spmv["lds_tile" if g == 1 else str(g)] = {"ms": round(ms, 4), "GBps": round(nbytes / ms / 1e6, 1)}
     it = np.array([i["iters"] for i in infos])
     print(json.dumps({
-        "workload": "64 Klein-step 2+1D systems, n^3 with n ~ U{32..96}, V0 ~ U[0,3] (seed 0): assemble all + "
-                    "batched complex128 FGMRES(10) line PC, rtol 1e-8",
+        "workload": "64 Klein-step 2+1D systems, n^3 with n ~ U{32..96}, V0 ~ U[0,3] (seed 0): assemble all "
+                    "(complex128 blocks) + batched complex128 FGMRES(10) line PC, rtol 1e-8",
         "systems": len(ops), "block_rows": rows, "unknowns": 2 * rows,
         "step_ms": round(ms_step, 2), "steps": args.steps, "warmup": args.warmup,
         "converged": int(sum(i["converged"] for i in infos)),
@@ -318,7 +323,7 @@ def batch_bench(args):
         "max_rel_diff_fp32ir_vs_fp64": err,
         "autotuned_lanes": lanes,
         "grouped_spmv_c64": spmv, "grouped_spmv_bytes": nbytes,
-        "memory_GB": round((sum(op.bytes() for op in ops) + work.numel()) / 1e9, 2),
+        "memory_GB": round((sum(op.bytes() for op in ops + ops64) + work.numel()) / 1e9, 2),
     }))
 
 
