@@ -17,11 +17,13 @@
 // Basis vectors are stored unnormalised with a scale sigma_k kept in FP64,
 // so no separate normalisation pass is needed.
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 
 #include "common.hpp"
 #include "krylov.hpp"
 #include "nn_host.hpp"
+#include "readback.hpp"
 #include "precond.hpp"
 #include "spectral.hpp"
 #include "mfspmv.hpp"
@@ -161,6 +163,7 @@ static int pc_apply(const Precond &P, const cx<T> *v, cx<T> *z, double scale, in
 struct Readback {
   double est_abs, happy, finite, sigma_next;
 };
+static_assert(sizeof(Readback) <= 8 * sizeof(double), "fits the solver's readback buffers");
 
 template <typename T>
 static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const dirac_st_opts *o,
@@ -193,13 +196,16 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   zero_ctrl<<<8, 256, 0, s>>>(ctrl);
   DST_LAUNCHED();
 
+  // scalar readbacks land in page-locked memory when it is available
+  double local_rb[8];
+  double *const hrb = readback_buffer() ? readback_buffer() : local_rb;
   auto read_norm = [&](const double2 *v, double &out) -> int {
     norm_pass<double><<<nblocks(N), 256, 0, s>>>(v, partial, N);
     reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
     DST_LAUNCHED();
-    DST_HIP(hipMemcpyAsync(&out, &ctrl->dots_norm2, sizeof(double), hipMemcpyDeviceToHost, s));
+    DST_HIP(hipMemcpyAsync(hrb, &ctrl->dots_norm2, sizeof(double), hipMemcpyDeviceToHost, s));
     DST_HIP(hipStreamSynchronize(s));
-    out = sqrt(out);
+    out = sqrt(hrb[0]);
     return 0;
   };
 
@@ -214,7 +220,8 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   double relres_prev = -1.0;
 
   // a zero initial guess needs no first SpMV: its residual is b.  ||x||^2 and
-  // ||b||^2 come back in one read (the norm^2 slot and the estimate slot)
+  // ||b||^2 come back in one copy (the estimate slot and the norm^2 slot,
+  // which the control block keeps two doubles apart)
   double xnorm = 0.0, bnorm = 0.0;
   {
     norm_pass<double><<<nblocks(N), 256, 0, s>>>(x, partial, N);
@@ -223,12 +230,12 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
     norm_pass<double><<<nblocks(N), 256, 0, s>>>(b, partial, N);
     reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
     DST_LAUNCHED();
-    double both[2];
-    DST_HIP(hipMemcpyAsync(&both[0], &ctrl->est_abs, sizeof(double), hipMemcpyDeviceToHost, s));
-    DST_HIP(hipMemcpyAsync(&both[1], &ctrl->dots_norm2, sizeof(double), hipMemcpyDeviceToHost, s));
+    static_assert(offsetof(Ctrl, est_abs) == offsetof(Ctrl, dots_norm2) + 2 * sizeof(double),
+                  "norm^2 and estimate slots");
+    DST_HIP(hipMemcpyAsync(hrb, &ctrl->dots_norm2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     DST_HIP(hipStreamSynchronize(s));
-    xnorm = sqrt(both[0]);
-    bnorm = sqrt(both[1]);
+    xnorm = sqrt(hrb[2]);
+    bnorm = sqrt(hrb[0]);
   }
   bool x_zero = xnorm == 0.0;
   if (!std::isfinite(bnorm)) {
@@ -321,8 +328,9 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
       givens_step<<<1, 64, 0, s>>>(ctrl, j);
       DST_LAUNCHED();
       Readback rb{};
-      DST_HIP(hipMemcpyAsync(&rb, &ctrl->est_abs, sizeof(rb), hipMemcpyDeviceToHost, s));
+      DST_HIP(hipMemcpyAsync(hrb, &ctrl->est_abs, sizeof(rb), hipMemcpyDeviceToHost, s));
       DST_HIP(hipStreamSynchronize(s));
+      memcpy(&rb, hrb, sizeof(rb));
       its++;
       k = j + 1;
       const double est = rb.est_abs / bnorm;
