@@ -27,6 +27,7 @@
 #include "common.hpp"
 #include "krylov.hpp"
 #include "precond.hpp"
+#include "readback.hpp"
 #include "spectral.hpp"
 #include "spmv.hpp"
 
@@ -301,6 +302,12 @@ struct LineSetupJob {
   int64_t lines;
   int *flag;
 };
+
+// the line-setup flags of all systems into one array (one read-back)
+__global__ void g_line_flags(const LineSetupJob *__restrict__ J, int nsys, int *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsys) out[i] = *J[i].flag;
+}
 
 template <typename T, int NC, int DS>
 __global__ __launch_bounds__(64) void g_line_setup(const LineSetupJob *__restrict__ J, WorkList L) {
@@ -762,11 +769,15 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
   for (int i = 0; i < nsys; i++) stats[i].est = 0.0;
   std::vector<double> bnorm(nsys, 0.0), relres(nsys, 1.0), rb(5 * (size_t)nsys);
   std::vector<int> its(nsys, 0), cycles(nsys, 0), conv(nsys, 0), broke(nsys, 0);
+  // read-backs land in page-locked memory when it is available
+  double *const pinned = (double *)readback_buffer(sizeof(double) * 5 * (size_t)nsys);
   auto gather = [&](int nact) -> int {
     g_gather<<<(nact + 63) / 64, 64, 0, s>>>(dS, lists.w.act, nact, dGat);
     DST_LAUNCHED();
-    DST_HIP(hipMemcpyAsync(rb.data(), dGat, sizeof(double) * 5 * nact, hipMemcpyDeviceToHost, s));
+    double *dst = pinned ? pinned : rb.data();
+    DST_HIP(hipMemcpyAsync(dst, dGat, sizeof(double) * 5 * nact, hipMemcpyDeviceToHost, s));
     DST_HIP(hipStreamSynchronize(s));
+    if (pinned) std::copy(pinned, pinned + 5 * (size_t)nact, rb.begin());
     return 0;
   };
   // norms of the listed systems into rb[5a + 4] (and ctrl->dots_norm2):
@@ -789,9 +800,13 @@ static int batched_impl(int nsys, const dirac_st_bsr *const *A, const void *cons
     else g_line_setup<T, 4, 3><<<lists.nph[3], 64, 0, s>>>(dSJ, lists.ph[3]);
     DST_LAUNCHED();
     std::vector<int> bad(nsys, 0);
-    for (int i = 0; i < nsys; i++)
-      DST_HIP(hipMemcpyAsync(&bad[i], sjobs[i].flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    static_assert(sizeof(int) <= 5 * sizeof(double), "flags fit the gather area");
+    g_line_flags<<<(nsys + 63) / 64, 64, 0, s>>>(dSJ, nsys, (int *)dGat);
+    DST_LAUNCHED();
+    int *fdst = pinned ? (int *)pinned : bad.data();
+    DST_HIP(hipMemcpyAsync(fdst, dGat, sizeof(int) * nsys, hipMemcpyDeviceToHost, s));
     DST_HIP(hipStreamSynchronize(s));
+    if (pinned) std::copy((int *)pinned, (int *)pinned + nsys, bad.begin());
     for (int i = 0; i < nsys; i++)
       DST_CHECK(bad[i] == 0, "system %d: line preconditioner has %d singular line factorisations", i, bad[i]);
     staging.clear();

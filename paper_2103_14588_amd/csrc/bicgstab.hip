@@ -18,10 +18,12 @@
 // from the true residual with rh = r.  A restart that is hit again before
 // any iteration completes ends the solve as a breakdown.
 #include <chrono>
+#include <cstring>
 #include <cmath>
 
 #include "common.hpp"
 #include "krylov.hpp"
+#include "readback.hpp"
 #include "precond.hpp"
 #include "mfspmv.hpp"
 #include "spmv.hpp"
@@ -262,12 +264,17 @@ static int bicgstab_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, co
   S.relres = S.est = 0.0;
   S.fallback = 0;
 
+  // scalar readbacks land in page-locked memory when it is available
+  double local_rb[8];
+  double *const pinned = (double *)readback_buffer(sizeof(local_rb));
+  double *const hrb = pinned ? pinned : local_rb;
   auto norm2 = [&](const double2 *a, double &out) -> int {
     bi_dot<true><<<g, 256, 0, s>>>(a, a, partial, N, nblk);
     bi_reduce<2><<<1, 256, 0, s>>>(partial, nblk, c, 3);
     DST_LAUNCHED();
-    DST_HIP(hipMemcpyAsync(&out, &c->est2, sizeof(double), hipMemcpyDeviceToHost, s));
+    DST_HIP(hipMemcpyAsync(hrb, &c->est2, sizeof(double), hipMemcpyDeviceToHost, s));
     DST_HIP(hipStreamSynchronize(s));
+    out = hrb[0];
     return 0;
   };
   double bn2 = 0.0, xn2 = 0.0;
@@ -340,8 +347,10 @@ static int bicgstab_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, co
       bi_reduce<2><<<1, 256, 0, s>>>(partial, nblk, c, 2);
       DST_LAUNCHED();
       BiReadback rb{};
-      DST_HIP(hipMemcpyAsync(&rb, &c->est2, sizeof(rb), hipMemcpyDeviceToHost, s));
+      static_assert(sizeof(rb) <= sizeof(local_rb), "fits the readback buffer");
+      DST_HIP(hipMemcpyAsync(hrb, &c->est2, sizeof(rb), hipMemcpyDeviceToHost, s));
       DST_HIP(hipStreamSynchronize(s));
+      memcpy(&rb, hrb, sizeof(rb));
       // rh^H v = 0: alpha and omega were set to zero, x and r are unchanged;
       // restart without counting a step
       if (rb.flag == 1.0) break;

@@ -198,7 +198,8 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
 
   // scalar readbacks land in page-locked memory when it is available
   double local_rb[8];
-  double *const hrb = readback_buffer() ? readback_buffer() : local_rb;
+  double *const pinned = (double *)readback_buffer(sizeof(local_rb));
+  double *const hrb = pinned ? pinned : local_rb;
   auto read_norm = [&](const double2 *v, double &out) -> int {
     norm_pass<double><<<nblocks(N), 256, 0, s>>>(v, partial, N);
     reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);

@@ -1,25 +1,34 @@
 // readback.hpp -- page-locked host memory for the solvers' scalar readbacks.
 #pragma once
 
+#include <cstddef>
+
 #include <hip/hip_runtime.h>
 
 namespace dst {
 
-// A small page-locked host buffer per host thread, allocated on first use and
-// kept for the life of the process.  The solvers copy their convergence
-// scalars (norms, residual estimates, breakdown flags) into it before each
-// host decision: a device-to-host copy into pageable memory is staged through
-// a driver buffer and adds a round trip to every such decision.  Returns
-// nullptr if the allocation failed; the caller then reads into its own memory.
-constexpr int kReadbackDoubles = 64;
-inline double *readback_buffer() {
-  thread_local double *p = nullptr;
-  thread_local bool tried = false;
-  if (!tried) {
-    tried = true;
-    if (hipHostMalloc((void **)&p, kReadbackDoubles * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+// A page-locked host buffer per host thread of at least `bytes`, allocated on
+// first use, grown when a larger one is asked for and kept for the life of
+// the process.  The solvers copy their convergence scalars (norms, residual
+// estimates, breakdown flags) into it before each host decision: a
+// device-to-host copy into pageable memory is staged through a driver buffer
+// and adds a round trip to every such decision.  Every use waits for its
+// copy before returning, so no copy is in flight when the buffer is replaced.
+// Returns nullptr if the allocation failed; the caller then reads into its
+// own memory.
+inline void *readback_buffer(size_t bytes) {
+  thread_local void *p = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    const size_t want = bytes < 4096 ? 4096 : bytes;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) == hipSuccess) {
+      cap = want;
+    } else {
       p = nullptr;
-      (void)hipGetLastError();  // the failure is handled here, not by the next call's check
+      (void)hipGetLastError();  // handled here, not reported by the next call's check
     }
   }
   return p;
