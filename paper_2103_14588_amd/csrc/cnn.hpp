@@ -343,86 +343,132 @@ void conv3d_mfma(Grid3 g, const uint16_t *__restrict__ in,
 
 // Partial weight gradients dW[tap][ci][co] = sum_p act[p + tap][ci] gout[p][co]
 // over the tiles a workgroup visits; one FP32 row of 27*CIN*COUT per workgroup
-// (written in full, zeros included).  MFMA rows = (tap, ci), columns = co,
-// K = voxels (16 per MFMA).  Wavefront w owns row tiles w, w+4, ...
+// (written in full, zeros included).  GEMM with M = (tap, ci), N = co (16,
+// zero-padded for COUT 4) and K = voxels, 32 per v_mfma_f32_16x16x32_bf16: a
+// K step covers two 16-voxel x-rows of the tile, lane group kg holding
+// voxels x = 8 (kg & 1) .. + 7 of row kg >> 1 in both operands.  Both
+// operands are staged channel-major so that these 8 voxels are 16 contiguous
+// bytes: the output gradient as gT[co][t][y][x], the activations as three
+// copies of the halo shifted by 0, 1, 2 voxels along x,
+//   cp[s][ci][a][b][j] = halo[ci][a][b][j + s], j < 16,
+// so that the operand of any tap (shift s = dx + 1) is one aligned 16-byte
+// read.  Row tiles: CIN 16 -> one tap (m = ci), wavefront w owns taps w, w+4,
+// ...; CIN 4 -> four taps (m = 4 (tap % 4) + ci), row tile r = taps 4r..4r+3.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void conv3d_wgrad(Grid3 g, const uint16_t *__restrict__ act,
                                                     const uint16_t *__restrict__ gout,
                                                     float *__restrict__ partial) {
+  static_assert(CIN == 4 || CIN == 16, "cin");
+  static_assert(COUT == 4 || COUT == 16, "cout");
   constexpr int NROWT = CIN == 16 ? 27 : 7;   // row tiles of 16 (tap, ci) rows
   constexpr int PERW = (NROWT + 3) / 4;        // row tiles per wavefront
-  __shared__ __attribute__((aligned(16))) uint16_t halo[HT * HY * HX * CIN];
-  __shared__ __attribute__((aligned(16))) uint16_t gt[TT * TY * TX * 16];
+  constexpr int HROW = 16;                     // elements per staged x-row
+  constexpr int CP = CIN * HT * HY * HROW;     // elements per shifted copy
+  __shared__ __attribute__((aligned(16))) uint16_t cp[3 * CP];
+  __shared__ __attribute__((aligned(16))) uint16_t gT[16 * TT * TY * TX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mrow = lane & 15, kg = lane >> 4;
+  // output-gradient channels >= COUT stay zero
+  for (int e = threadIdx.x; e < 16 * TT * TY * TX; e += 256) gT[e] = 0;
   f4v acc[PERW];
 #pragma unroll
   for (int q = 0; q < PERW; q++) acc[q] = {0.f, 0.f, 0.f, 0.f};
-  const int64_t ntiles = (int64_t)g.tiles_t * g.tiles_y * g.tiles_x;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // the next tile's activations and output gradient are fetched into
+  // registers while the current tile's MFMAs run
+  uint4 pre[kHaloRounds][2], pg[2];
+  unsigned okm = 0;
+  auto fetch_gout = [&](int tile) {
     int t0, y0, x0;
     tile_origin(g, tile, t0, y0, x0);
-    __syncthreads();
-    for (int hv = threadIdx.x; hv < HT * HY * HX; hv += 256) {
+    const int v = threadIdx.x;
+    const int x = v % TX, y = (v / TX) % TY, t = v / (TX * TY);
+    const int gx = x0 + x, gy = y0 + y, gtt = t0 + t;
+    const bool ok = gx < g.nx && gy < g.ny && gtt < g.nt;  // 0 outside the grid
+    const int64_t vox = ok ? ((int64_t)gtt * g.ny + gy) * g.nx + gx : 0;
+    if constexpr (COUT == 16) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(gout + vox * 16);
+      pg[0] = src[0];
+      pg[1] = src[1];
+    } else {
+      const uint2 q = *reinterpret_cast<const uint2 *>(gout + vox * 4);
+      pg[0] = make_uint4(q.x, q.y, 0, 0);
+      pg[1] = make_uint4(0, 0, 0, 0);
+    }
+    if (!ok) pg[0] = pg[1] = make_uint4(0, 0, 0, 0);
+  };
+  const int ntiles = g.tiles_t * g.tiles_y * g.tiles_x;
+  if ((int)blockIdx.x < ntiles) {
+    okm = halo_fetch<CIN>(g, blockIdx.x, act, pre);
+    fetch_gout(blockIdx.x);
+  }
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();  // the previous tile's operands are consumed
+    // activations: halo voxel (a, b, c) goes to copy s at j = c - s
+#pragma unroll
+    for (int u = 0; u < kHaloRounds; u++) {
+      const int hv = threadIdx.x + 256 * u;
+      if (hv >= kHaloVox) continue;
       const int c = hv % HX, b = (hv / HX) % HY, a = hv / (HX * HY);
-      const int64_t vox = halo_voxel(g, t0, y0, x0, a, b, c);
-      uint16_t *dst = halo + hv * CIN;
-      if (CIN == 16) {
-        uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
-        if (vox >= 0) {
-          const uint4 *src = reinterpret_cast<const uint4 *>(act + vox * 16);
-          q0 = src[0];
-          q1 = src[1];
-        }
-        reinterpret_cast<uint4 *>(dst)[0] = q0;
-        reinterpret_cast<uint4 *>(dst)[1] = q1;
-      } else {
-        uint2 q = make_uint2(0, 0);
-        if (vox >= 0) q = *reinterpret_cast<const uint2 *>(act + vox * 4);
-        *reinterpret_cast<uint2 *>(dst) = q;
+      const uint4 z = make_uint4(0, 0, 0, 0);
+      const uint4 q0 = (okm >> u) & 1 ? pre[u][0] : z, q1 = (okm >> u) & 1 ? pre[u][1] : z;
+      const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+      uint16_t v[CIN];
+#pragma unroll
+      for (int i = 0; i < CIN / 2; i++) {
+        v[2 * i] = (uint16_t)(w[i] & 0xFFFFu);
+        v[2 * i + 1] = (uint16_t)(w[i] >> 16);
+      }
+#pragma unroll
+      for (int sft = 0; sft < 3; sft++) {
+        const int j = c - sft;
+        if (j < 0 || j >= HROW) continue;
+#pragma unroll
+        for (int ci = 0; ci < CIN; ci++) cp[sft * CP + ((ci * HT + a) * HY + b) * HROW + j] = v[ci];
       }
     }
-    // output-gradient tile [voxel][16] (channels >= COUT and voxels outside the grid are 0)
+    // output gradient: voxel v of the tile (t, y, x) = (v / 64, v / 16 % 4, v % 16)
     {
-      const int v = threadIdx.x;  // 256 voxels, one per thread
-      const int x = v % TX, y = (v / TX) % TY, t = v / (TX * TY);
-      const int gx = x0 + x, gy = y0 + y, gtt = t0 + t;
-      const bool ok = gx < g.nx && gy < g.ny && gtt < g.nt;
-      const int64_t vox = ((int64_t)gtt * g.ny + gy) * g.nx + gx;
+      const int v = threadIdx.x;
+      const uint32_t w[8] = {pg[0].x, pg[0].y, pg[0].z, pg[0].w, pg[1].x, pg[1].y, pg[1].z, pg[1].w};
 #pragma unroll
-      for (int c = 0; c < 16; c++) gt[v * 16 + c] = (ok && c < COUT) ? gout[vox * COUT + c] : (uint16_t)0;
+      for (int i = 0; i < COUT / 2; i++) {
+        gT[(2 * i) * 256 + v] = (uint16_t)(w[i] & 0xFFFFu);
+        gT[(2 * i + 1) * 256 + v] = (uint16_t)(w[i] >> 16);
+      }
     }
     __syncthreads();
-    // K loop over the tile's voxels in chunks of 16 (one y-row of x)
-    for (int kc = 0; kc < TT * TY; kc++) {
-      const int tl = kc / TY, r = kc % TY;
-      // B[k = voxel][n = co]: voxels 4 kg + i of this row, channel mrow
-      s4v bb;
-#pragma unroll
-      for (int i = 0; i < 4; i++) bb[i] = (short)gt[(kc * TX + 4 * kg + i) * 16 + mrow];
+    {
+      const int next = tile + (int)gridDim.x;
+      const int nt = next < ntiles ? next : tile;  // unconditional: fixed load count
+      okm = halo_fetch<CIN>(g, nt, act, pre);
+      fetch_gout(nt);
+    }
+    // K steps: step k covers tau slice k / 2, y-rows 2 (k % 2) and 2 (k % 2) + 1
+    const int h = kg & 1;
+#pragma unroll 2
+    for (int k = 0; k < TT * TY / 2; k++) {
+      const int t = k >> 1, y = 2 * (k & 1) + (kg >> 1);
+      const bf8v bb = __builtin_bit_cast(bf8v, *reinterpret_cast<const s8v *>(
+                                                   gT + mrow * 256 + (t * TY + y) * TX + 8 * h));
 #pragma unroll
       for (int q = 0; q < PERW; q++) {
         const int rt = wave + 4 * q;
         if (rt >= NROWT) continue;
-        // A[m = row][k = voxel]: row = (tap, ci)
         int tap, ci;
         if (CIN == 16) {
           tap = rt;
           ci = mrow;
         } else {
-          tap = 4 * rt + mrow / 4;
-          ci = mrow % 4;
+          tap = 4 * rt + (mrow >> 2);
+          ci = mrow & 3;
         }
-        s4v aa = {0, 0, 0, 0};
+        s8v aa = {0, 0, 0, 0, 0, 0, 0, 0};
         if (tap < 27) {
           const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-#pragma unroll
-          for (int i = 0; i < 4; i++) {
-            const int hv = ((tl + 1 + dt) * HY + (r + 1 + dy)) * HX + (4 * kg + i + 1 + dx);
-            aa[i] = (short)halo[hv * CIN + ci];
-          }
+          aa = *reinterpret_cast<const s8v *>(
+              cp + (dx + 1) * CP + ((ci * HT + (t + 1 + dt)) * HY + (y + 1 + dy)) * HROW + 8 * h);
         }
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aa, bb, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, aa), bb, acc[q], 0, 0, 0);
       }
     }
   }
