@@ -352,7 +352,9 @@ void conv3d_mfma(Grid3 g, const uint16_t *__restrict__ in,
 // copies of the halo shifted by 0, 1, 2 voxels along x,
 //   cp[s][ci][a][b][j] = halo[ci][a][b][j + s], j < 16,
 // so that the operand of any tap (shift s = dx + 1) is one aligned 16-byte
-// read.  Row tiles: CIN 16 -> one tap (m = ci), wavefront w owns taps w, w+4,
+// read.  Each channel plane is padded by 16 bytes: the 16 lanes of a read
+// differ only in the channel, and unpadded planes (multiples of 128 bytes)
+// would put all of them on the same LDS banks.  Row tiles: CIN 16 -> one tap (m = ci), wavefront w owns taps w, w+4,
 // ...; CIN 4 -> four taps (m = 4 (tap % 4) + ci), row tile r = taps 4r..4r+3.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void conv3d_wgrad(Grid3 g, const uint16_t *__restrict__ act,
@@ -363,13 +365,15 @@ __global__ __launch_bounds__(256) void conv3d_wgrad(Grid3 g, const uint16_t *__r
   constexpr int NROWT = CIN == 16 ? 27 : 7;   // row tiles of 16 (tap, ci) rows
   constexpr int PERW = (NROWT + 3) / 4;        // row tiles per wavefront
   constexpr int HROW = 16;                     // elements per staged x-row
-  constexpr int CP = CIN * HT * HY * HROW;     // elements per shifted copy
+  constexpr int CHS = HT * HY * HROW + 8;      // elements per channel plane (padded)
+  constexpr int CP = CIN * CHS;                // elements per shifted copy
+  constexpr int GS = TT * TY * TX + 8;         // elements per output-gradient plane (padded)
   __shared__ __attribute__((aligned(16))) uint16_t cp[3 * CP];
-  __shared__ __attribute__((aligned(16))) uint16_t gT[16 * TT * TY * TX];
+  __shared__ __attribute__((aligned(16))) uint16_t gT[16 * GS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mrow = lane & 15, kg = lane >> 4;
   // output-gradient channels >= COUT stay zero
-  for (int e = threadIdx.x; e < 16 * TT * TY * TX; e += 256) gT[e] = 0;
+  for (int e = threadIdx.x; e < 16 * GS; e += 256) gT[e] = 0;
   f4v acc[PERW];
 #pragma unroll
   for (int q = 0; q < PERW; q++) acc[q] = {0.f, 0.f, 0.f, 0.f};
@@ -423,7 +427,7 @@ __global__ __launch_bounds__(256) void conv3d_wgrad(Grid3 g, const uint16_t *__r
         const int j = c - sft;
         if (j < 0 || j >= HROW) continue;
 #pragma unroll
-        for (int ci = 0; ci < CIN; ci++) cp[sft * CP + ((ci * HT + a) * HY + b) * HROW + j] = v[ci];
+        for (int ci = 0; ci < CIN; ci++) cp[sft * CP + ci * CHS + (a * HY + b) * HROW + j] = v[ci];
       }
     }
     // output gradient: voxel v of the tile (t, y, x) = (v / 64, v / 16 % 4, v % 16)
@@ -432,8 +436,8 @@ __global__ __launch_bounds__(256) void conv3d_wgrad(Grid3 g, const uint16_t *__r
       const uint32_t w[8] = {pg[0].x, pg[0].y, pg[0].z, pg[0].w, pg[1].x, pg[1].y, pg[1].z, pg[1].w};
 #pragma unroll
       for (int i = 0; i < COUT / 2; i++) {
-        gT[(2 * i) * 256 + v] = (uint16_t)(w[i] & 0xFFFFu);
-        gT[(2 * i + 1) * 256 + v] = (uint16_t)(w[i] >> 16);
+        gT[(2 * i) * GS + v] = (uint16_t)(w[i] & 0xFFFFu);
+        gT[(2 * i + 1) * GS + v] = (uint16_t)(w[i] >> 16);
       }
     }
     __syncthreads();
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(256) void conv3d_wgrad(Grid3 g, const uint16_t *__r
     for (int k = 0; k < TT * TY / 2; k++) {
       const int t = k >> 1, y = 2 * (k & 1) + (kg >> 1);
       const bf8v bb = __builtin_bit_cast(bf8v, *reinterpret_cast<const s8v *>(
-                                                   gT + mrow * 256 + (t * TY + y) * TX + 8 * h));
+                                                   gT + mrow * GS + (t * TY + y) * TX + 8 * h));
 #pragma unroll
       for (int q = 0; q < PERW; q++) {
         const int rt = wave + 4 * q;
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(256) void conv3d_wgrad(Grid3 g, const uint16_t *__r
         if (tap < 27) {
           const int dt = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
           aa = *reinterpret_cast<const s8v *>(
-              cp + (dx + 1) * CP + ((ci * HT + (t + 1 + dt)) * HY + (y + 1 + dy)) * HROW + 8 * h);
+              cp + (dx + 1) * CP + ci * CHS + ((t + 1 + dt) * HY + (y + 1 + dy)) * HROW + 8 * h);
         }
         acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, aa), bb, acc[q], 0, 0, 0);
       }
