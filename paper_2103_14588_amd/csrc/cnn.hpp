@@ -203,7 +203,11 @@ void conv3d_mfma(Grid3 g, const uint16_t *__restrict__ in,
   constexpr int NS = ConvSteps<CIN>::N;
   constexpr int HB = kHaloVox * CIN;  // elements per halo buffer
   __shared__ __attribute__((aligned(16))) uint16_t halo[2 * HB];
-  __shared__ __attribute__((aligned(16))) uint16_t ep[4][256];  // per-wavefront output transpose
+  // per-wavefront output transpose: 16 voxel rows of 16 bf16 channels, rows
+  // EPR = 20 elements apart so that the four lane groups (4 voxels apart) of
+  // a write land on disjoint LDS banks
+  constexpr int EPR = 20;
+  __shared__ __attribute__((aligned(16))) uint16_t ep[4][16 * EPR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mrow = lane & 15, kg = lane >> 4;
   const int ntiles = g.tiles_t * g.tiles_y * g.tiles_x;
@@ -316,11 +320,13 @@ void conv3d_mfma(Grid3 g, const uint16_t *__restrict__ in,
           float v = acc[r][i];
           // written so that NaN propagates (a broken network must show)
           if (MODE == CONV_RELU) v = (v + bco) <= 0.f ? 0.f : v + bco;
-          e[(4 * kg + i) * 16 + co] = f2bf(v);
+          e[(4 * kg + i) * EPR + co] = f2bf(v);
         }
         if (lane < 32 && x0 + xv < g.nx) {
           const int64_t o = (row + x0 + xv) * 16 + 8 * half;
-          uint4 q = reinterpret_cast<const uint4 *>(e)[lane];
+          const uint2 lo = *reinterpret_cast<const uint2 *>(e + xv * EPR + 8 * half);
+          const uint2 hi = *reinterpret_cast<const uint2 *>(e + xv * EPR + 8 * half + 4);
+          uint4 q = make_uint4(lo.x, lo.y, hi.x, hi.y);
           if constexpr (MODE == CONV_BWD) {
             // ReLU adjoint: keep the gradient where the forward activation was positive
             const uint4 m = mk[r];
