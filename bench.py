@@ -95,7 +95,13 @@ def cpu_baseline(wl, x_gpu_list):
     sec = time.perf_counter() - t0
     errs = [float(np.linalg.norm(xg - x) / np.linalg.norm(x)) for xg in x_gpu_list]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": sec * 1e3, "unit": "ms", "cores": cores, "kind": "oracle",
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), cpu_model)
+    except OSError:
+        pass
+    return {"value": sec * 1e3, "unit": "ms", "cores": cores, "cpu_model": cpu_model, "kind": "oracle",
             "sample": "full workload: oracle element-loop assembly + GMRES(%d) spectral PC to %g "
                       "(%d iterations, relres %.2e)" % (wl.restart, wl.rtol, info["iters"], info["relres"])}, errs
 
@@ -477,6 +483,13 @@ def main():
     # coefficients are computed, not read)
     t_mf64 = time_launches(lambda: D.spmv_mf(op, xx, yy), reps, torch)
     t_mf32 = time_launches(lambda: D.spmv_mf(op, xx32, yy32), reps, torch)
+    # achievable bandwidth of a plain device copy on this GPU (2 GiB read + 2 GiB
+    # written by torch's copy kernel), reported beside the fractions of peak
+    cbig = torch.empty(2 ** 31 // 16, dtype=torch.complex128, device="cuda")
+    cdst = torch.empty_like(cbig)
+    t_copy = time_launches(lambda: cdst.copy_(cbig), 5, torch)
+    copy_gbs = 2 * cbig.numel() * 16 / t_copy / 1e6
+    del cbig, cdst
     by64, by32 = spmv_bytes(op, 16), spmv_bytes(op, 8)
     gbs64, gbs32 = by64 / t_spmv64 / 1e6, by32 / t_spmv32 / 1e6
     asm_bytes = op.bytes() + op.n * 16 + psi0.numel() * 16
@@ -531,7 +544,10 @@ def main():
                        "spmv_matrix_free_c128": round(t_mf64, 4), "spmv_matrix_free_c64": round(t_mf32, 4)},
         "spmv": {"c128_GBps": round(gbs64, 1), "c64_GBps": round(gbs32, 1),
                  "c128_frac": round(gbs64 / HBM_PEAK_GBS, 4), "c64_frac": round(gbs32 / HBM_PEAK_GBS, 4),
-                 "c128_bytes": by64, "c64_bytes": by32},
+                 "c128_bytes": by64, "c64_bytes": by32,
+                 "device_copy_2GiB_GBps": round(copy_gbs, 1),
+                 "c128_frac_of_device_copy": round(gbs64 / copy_gbs, 4),
+                 "c128_in_step_frac_of_device_copy": round(by64 / l_spmv / 1e6 / copy_gbs, 4)},
         "roofline": {"kernel": rl_kernel, "bound": "hbm",
                      "achieved": round(g_live, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(g_live / HBM_PEAK_GBS, 4),
