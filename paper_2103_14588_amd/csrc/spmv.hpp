@@ -320,6 +320,15 @@ __device__ __forceinline__ void spmv_tile_lds(int64_t tile, const Stencil &g, co
       }
     }
   }
+  // residual form: the right-hand side entries this lane writes are loaded
+  // with the values, not after the products (a load issued at the end would
+  // add one memory latency to every workgroup)
+  cx<T> bpre[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; r++) {
+    bpre[r] = mk<cx<T>>(0, 0);
+    if (RESID && xr0 + r < n1 && lane == i * IB) bpre[r] = bvec[(line * n1 + xr0 + r) * NC + i];
+  }
   // stage x: chunk e = ((kt NY + ly) TW + lx) IB + c
   for (int e = threadIdx.x; e < ntime * NY * TW * IB; e += 256) {
     const int c = e % IB, node = e / IB;
@@ -383,8 +392,7 @@ __device__ __forceinline__ void spmv_tile_lds(int64_t tile, const Stencil &g, co
     if (own && lane == i * IB) {
       const int64_t o = (line * n1 + xr) * NC + i;
       if (RESID) {
-        cx<T> bb = bvec[o];
-        y[o] = mk<cx<T>>(bb.x - acc.x, bb.y - acc.y);
+        y[o] = mk<cx<T>>(bpre[r].x - acc.x, bpre[r].y - acc.y);
       } else {
         y[o] = mk<cx<T>>(alpha * acc.x, alpha * acc.y);
       }
