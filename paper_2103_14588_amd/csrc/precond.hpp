@@ -9,12 +9,17 @@
 #pragma once
 
 #include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <utility>
 #include <vector>
 
 #include "common.hpp"
 #include "krylov.hpp"
 #include "linepc.hpp"
+#include "readback.hpp"
 #include "spectral.hpp"
 #include "time_eigen.hpp"
 
@@ -105,19 +110,165 @@ static double host_potential(const dirac_st_problem *p, double x) {
   return 0.0;
 }
 
+// Host tables of the line preconditioner for one (problem, precision, time
+// slabs): twiddles, time eigen-decomposition, 1D potential matrix and the
+// transverse DFT matrices, packed in one page-locked block together with each
+// piece's offset in the workspace.  They depend on nothing else, so a set-up
+// of a problem seen before only uploads them (asynchronously: copies from
+// page-locked memory do not stage through the driver).
+struct LineTables {
+  struct Piece {
+    size_t dev, host, bytes;
+  };
+  std::vector<Piece> pieces;
+  unsigned char *host = nullptr;
+  bool pinned = false;
+  LineTables() = default;
+  LineTables(const LineTables &) = delete;
+  LineTables &operator=(const LineTables &) = delete;
+  ~LineTables() {
+    if (!host) return;
+    if (pinned) (void)hipHostFree(host);
+    else delete[] host;
+  }
+};
+
 // Host-side data of one line preconditioner set-up; kept alive until the
 // stream has consumed the asynchronous copies made from it.
 struct LineStaging {
-  std::vector<double2> tw64, l64, q64, w64;
-  std::vector<float2> tw32, q32, w32;
-  std::vector<double> pot;
-  std::vector<std::vector<double2>> f64s, fi64s;
-  std::vector<std::vector<float2>> f32s, fi32s;
+  std::shared_ptr<const LineTables> tables;
 };
 
+static int build_line_tables(const dirac_st_problem *p, const LineLayout &L, const SpecGeom &G,
+                             std::shared_ptr<LineTables> &out) {
+  std::vector<std::pair<size_t, std::vector<unsigned char>>> parts;  // (workspace offset, bytes)
+  auto add = [&](size_t off, const void *src, size_t bytes) {
+    const unsigned char *c = (const unsigned char *)src;
+    parts.emplace_back(off, std::vector<unsigned char>(c, c + bytes));
+  };
+  int64_t twn = 0;
+  for (int a = 1; a <= p->d; a++) twn += p->n[a];
+  std::vector<double2> tw64(twn, mk<double2>(0, 0));
+  std::vector<float2> tw32(twn, mk<float2>(0, 0));
+  for (int a = 1; a <= p->d; a++)
+    for (int q = 0; q < p->n[a]; q++) {
+      const double th = 2.0 * M_PI * (double)q / (double)p->n[a];
+      tw64[G.tw_off[a] + q] = mk<double2>(cos(th), -sin(th));
+      tw32[G.tw_off[a] + q] = mk<float2>((float)cos(th), (float)-sin(th));
+    }
+  add(L.tw64, tw64.data(), twn * sizeof(double2));
+  add(L.tw32, tw32.data(), twn * sizeof(float2));
+  // every slab has the pencil of a whole interval of tl rows (first row
+  // interior-like, last row the end row), so one decomposition serves all
+  const int nt = p->n[0], n1 = p->n[1], tl = L.tl;
+  std::vector<std::complex<double>> lam, W, Q;
+  if (int rc = time_eigen(tl, p->len[0] / nt, lam, W, Q)) return rc;
+  std::vector<double2> q64((size_t)L.pm * L.pk, mk<double2>(0, 0)), w64 = q64;
+  std::vector<float2> q32(q64.size(), mk<float2>(0, 0)), w32 = q32;
+  std::vector<double2> l64(nt);  // eigenvalue of time row r: that of its row in the slab
+  for (int r = 0; r < nt; r++) l64[r] = mk<double2>(lam[r % tl].real(), lam[r % tl].imag());
+  for (int r = 0; r < tl; r++)
+    for (int c = 0; c < tl; c++) {
+      const size_t e = (size_t)r * L.pk + c;
+      const std::complex<double> qv = Q[(size_t)r * tl + c], wv = W[(size_t)r * tl + c];
+      q64[e] = mk<double2>(qv.real(), qv.imag());
+      w64[e] = mk<double2>(wv.real(), wv.imag());
+      q32[e] = mk<float2>((float)qv.real(), (float)qv.imag());
+      w32[e] = mk<float2>((float)wv.real(), (float)wv.imag());
+    }
+  add(L.lam, l64.data(), l64.size() * sizeof(double2));
+  add(L.q64, q64.data(), q64.size() * sizeof(double2));
+  add(L.w64, w64.data(), w64.size() * sizeof(double2));
+  add(L.q32, q32.data(), q32.size() * sizeof(float2));
+  add(L.w32, w32.data(), w32.size() * sizeof(float2));
+  // P_x: diagonal and (i, i+1) entries, 2-point Gauss on every element
+  std::vector<double> pot(2 * (size_t)n1, 0.0);
+  const double h1 = p->len[1] / n1, r3 = 0.57735026918962576451;
+  for (int e = 0; e < n1; e++)
+    for (int q = 0; q < 2; q++) {
+      const double xi = 0.5 * (1.0 + (q ? r3 : -r3));
+      const double w = 0.5 * h1 * host_potential(p, (e + xi) * h1);
+      pot[e] += w * (1.0 - xi) * (1.0 - xi);
+      pot[(e + 1) % n1] += w * xi * xi;
+      pot[n1 + e] += w * (1.0 - xi) * xi;
+    }
+  add(L.pot, pot.data(), pot.size() * sizeof(double));
+  // DFT matrices of the transverse axes: F[k][j] = exp(-2 pi i k j / n),
+  // F^{-1}[j][k] = exp(2 pi i j k / n) / n
+  for (int a = 2; a <= p->d; a++) {
+    const int n = p->n[a], pk = L.dpk[a];
+    const size_t e = (size_t)L.dpm[a] * pk;
+    std::vector<double2> f64(e, mk<double2>(0, 0)), fi64 = f64;
+    std::vector<float2> f32(e, mk<float2>(0, 0)), fi32 = f32;
+    for (int k = 0; k < n; k++)
+      for (int j = 0; j < n; j++) {
+        const double th = 2.0 * M_PI * (double)((int64_t)k * j % n) / n;
+        const double c = cos(th), sn = sin(th);
+        f64[(size_t)k * pk + j] = mk<double2>(c, -sn);
+        fi64[(size_t)k * pk + j] = mk<double2>(c / n, sn / n);
+        f32[(size_t)k * pk + j] = mk<float2>((float)c, (float)-sn);
+        fi32[(size_t)k * pk + j] = mk<float2>((float)(c / n), (float)(sn / n));
+      }
+    add(L.f64[a], f64.data(), e * 16);
+    add(L.fi64[a], fi64.data(), e * 16);
+    add(L.f32[a], f32.data(), e * 8);
+    add(L.fi32[a], fi32.data(), e * 8);
+  }
+  auto T = std::make_shared<LineTables>();
+  size_t total = 0;
+  for (auto &pt : parts) total += align256(pt.second.size());
+  if (hipHostMalloc((void **)&T->host, total > 0 ? total : 1, hipHostMallocDefault) == hipSuccess) {
+    T->pinned = true;
+  } else {
+    (void)hipGetLastError();  // handled: the tables live in pageable memory instead
+    T->host = new unsigned char[total > 0 ? total : 1];
+  }
+  size_t h = 0;
+  for (auto &pt : parts) {
+    memcpy(T->host + h, pt.second.data(), pt.second.size());
+    T->pieces.push_back({pt.first, h, pt.second.size()});
+    h += align256(pt.second.size());
+  }
+  out = std::move(T);
+  return 0;
+}
+
+// Cached tables of (problem, precision, slabs); at most kLineTableCache
+// entries are kept (a set-up in flight holds its own reference).  The cache
+// is never destroyed: freeing page-locked memory from a static destructor
+// could run after the HIP runtime has shut down.
+constexpr size_t kLineTableCache = 256;
+static int line_tables(const dirac_st_problem *p, int prec, const LineLayout &L, const SpecGeom &G,
+                       std::shared_ptr<const LineTables> &out) {
+  static std::mutex &mu = *new std::mutex;
+  static auto &cache = *new std::map<std::vector<double>, std::shared_ptr<const LineTables>>;
+  std::vector<double> key = {(double)p->d, (double)p->nc, (double)p->vkind, p->m, p->v0, p->x0, p->lw,
+                             (double)prec, (double)L.slabs};
+  for (int a = 0; a < 4; a++) {
+    key.push_back((double)p->n[a]);
+    key.push_back(p->len[a]);
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto f = cache.find(key);
+    if (f != cache.end()) {
+      out = f->second;
+      return 0;
+    }
+  }
+  std::shared_ptr<LineTables> built;
+  if (int rc = build_line_tables(p, L, G, built)) return rc;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache.size() >= kLineTableCache) cache.clear();
+  cache[key] = built;
+  out = built;
+  return 0;
+}
+
 // Geometry, time eigen-decomposition, 1D potential matrix, DFT matrices:
-// computed on the host and copied (asynchronously) into the workspace; the
-// failure flag is cleared.  The factorisation itself is line_factor.
+// computed on the host (once per problem) and copied asynchronously into the
+// workspace; the failure flag is cleared.  The factorisation itself is
+// line_factor.
 template <typename T>
 static int line_prepare(Precond &P, const dirac_st_bsr *A, unsigned char *base, LineStaging &st,
                         hipStream_t s) {
@@ -128,85 +279,9 @@ static int line_prepare(Precond &P, const dirac_st_bsr *A, unsigned char *base, 
   P.LL = line_layout(p, P.prec, P.slabs);
   const LineLayout &L = P.LL;
   spec_geom(p, 0.0, P.G);
-  int64_t twn = 0;
-  for (int a = 1; a <= p->d; a++) twn += p->n[a];
-  st.tw64.assign(twn, mk<double2>(0, 0));
-  st.tw32.assign(twn, mk<float2>(0, 0));
-  for (int a = 1; a <= p->d; a++)
-    for (int q = 0; q < p->n[a]; q++) {
-      const double th = 2.0 * M_PI * (double)q / (double)p->n[a];
-      st.tw64[P.G.tw_off[a] + q] = mk<double2>(cos(th), -sin(th));
-      st.tw32[P.G.tw_off[a] + q] = mk<float2>((float)cos(th), (float)-sin(th));
-    }
-  // every slab has the pencil of a whole interval of tl rows (first row
-  // interior-like, last row the end row), so one decomposition serves all
-  const int nt = p->n[0], n1 = p->n[1], tl = L.tl;
-  std::vector<std::complex<double>> lam, W, Q;
-  if (int rc = time_eigen(tl, p->len[0] / nt, lam, W, Q)) return rc;
-  st.q64.assign((size_t)L.pm * L.pk, mk<double2>(0, 0));
-  st.w64.assign(st.q64.size(), mk<double2>(0, 0));
-  st.q32.assign(st.q64.size(), mk<float2>(0, 0));
-  st.w32.assign(st.q64.size(), mk<float2>(0, 0));
-  st.l64.resize(nt);  // eigenvalue of time row r: that of its row in the slab
-  for (int r = 0; r < nt; r++) st.l64[r] = mk<double2>(lam[r % tl].real(), lam[r % tl].imag());
-  for (int r = 0; r < tl; r++) {
-    for (int c = 0; c < tl; c++) {
-      const size_t e = (size_t)r * L.pk + c;
-      const std::complex<double> qv = Q[(size_t)r * tl + c], wv = W[(size_t)r * tl + c];
-      st.q64[e] = mk<double2>(qv.real(), qv.imag());
-      st.w64[e] = mk<double2>(wv.real(), wv.imag());
-      st.q32[e] = mk<float2>((float)qv.real(), (float)qv.imag());
-      st.w32[e] = mk<float2>((float)wv.real(), (float)wv.imag());
-    }
-  }
-  // P_x: diagonal and (i, i+1) entries, 2-point Gauss on every element
-  st.pot.assign(2 * (size_t)n1, 0.0);
-  const double h1 = p->len[1] / n1, r3 = 0.57735026918962576451;
-  for (int e = 0; e < n1; e++)
-    for (int q = 0; q < 2; q++) {
-      const double xi = 0.5 * (1.0 + (q ? r3 : -r3));
-      const double w = 0.5 * h1 * host_potential(p, (e + xi) * h1);
-      st.pot[e] += w * (1.0 - xi) * (1.0 - xi);
-      st.pot[(e + 1) % n1] += w * xi * xi;
-      st.pot[n1 + e] += w * (1.0 - xi) * xi;
-    }
-  auto up = [&](size_t off, const void *src, size_t bytes) -> int {
-    DST_HIP(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s));
-    return 0;
-  };
-  int rc = 0;
-  rc = rc ? rc : up(L.tw64, st.tw64.data(), twn * sizeof(double2));
-  rc = rc ? rc : up(L.tw32, st.tw32.data(), twn * sizeof(float2));
-  rc = rc ? rc : up(L.lam, st.l64.data(), st.l64.size() * sizeof(double2));
-  rc = rc ? rc : up(L.q64, st.q64.data(), st.q64.size() * sizeof(double2));
-  rc = rc ? rc : up(L.w64, st.w64.data(), st.w64.size() * sizeof(double2));
-  rc = rc ? rc : up(L.q32, st.q32.data(), st.q32.size() * sizeof(float2));
-  rc = rc ? rc : up(L.w32, st.w32.data(), st.w32.size() * sizeof(float2));
-  rc = rc ? rc : up(L.pot, st.pot.data(), st.pot.size() * sizeof(double));
-  if (rc) return rc;
-  // DFT matrices of the transverse axes: F[k][j] = exp(-2 pi i k j / n),
-  // F^{-1}[j][k] = exp(2 pi i j k / n) / n
-  for (int a = 2; a <= p->d; a++) {
-    const int n = p->n[a], pk = L.dpk[a];
-    const size_t e = (size_t)L.dpm[a] * pk;
-    st.f64s.emplace_back(e, mk<double2>(0, 0));
-    st.fi64s.emplace_back(e, mk<double2>(0, 0));
-    st.f32s.emplace_back(e, mk<float2>(0, 0));
-    st.fi32s.emplace_back(e, mk<float2>(0, 0));
-    for (int k = 0; k < n; k++)
-      for (int j = 0; j < n; j++) {
-        const double th = 2.0 * M_PI * (double)((int64_t)k * j % n) / n;
-        const double c = cos(th), sn = sin(th);
-        st.f64s.back()[(size_t)k * pk + j] = mk<double2>(c, -sn);
-        st.fi64s.back()[(size_t)k * pk + j] = mk<double2>(c / n, sn / n);
-        st.f32s.back()[(size_t)k * pk + j] = mk<float2>((float)c, (float)-sn);
-        st.fi32s.back()[(size_t)k * pk + j] = mk<float2>((float)(c / n), (float)(sn / n));
-      }
-    if ((rc = up(L.f64[a], st.f64s.back().data(), e * 16))) return rc;
-    if ((rc = up(L.fi64[a], st.fi64s.back().data(), e * 16))) return rc;
-    if ((rc = up(L.f32[a], st.f32s.back().data(), e * 8))) return rc;
-    if ((rc = up(L.fi32[a], st.fi32s.back().data(), e * 8))) return rc;
-  }
+  if (int rc = line_tables(p, P.prec, L, P.G, st.tables)) return rc;
+  for (const LineTables::Piece &pc : st.tables->pieces)
+    DST_HIP(hipMemcpyAsync(base + pc.dev, st.tables->host + pc.host, pc.bytes, hipMemcpyHostToDevice, s));
   zero_i32_flag<<<1, 64, 0, s>>>((int *)(base + L.flag));
   DST_LAUNCHED();
   return 0;
@@ -240,11 +315,13 @@ static int line_setup_host(Precond &P, const dirac_st_bsr *A, unsigned char *bas
   LineStaging st;
   if (int rc = line_prepare<T>(P, A, base, st, s)) return rc;
   if (int rc = line_factor<T>(P, s)) return rc;
-  int bad = 0;
-  DST_HIP(hipMemcpyAsync(&bad, base + P.LL.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  // the staging vectors live on this frame: wait for every copy
+  int local = 0;
+  int *const pinned = (int *)readback_buffer(sizeof(int));
+  int *const bad = pinned ? pinned : &local;
+  DST_HIP(hipMemcpyAsync(bad, base + P.LL.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  // the staging holds the uploaded tables: wait for every copy
   DST_HIP(hipStreamSynchronize(s));
-  DST_CHECK(bad == 0, "line preconditioner: %d singular or non-finite line factorisations", bad);
+  DST_CHECK(*bad == 0, "line preconditioner: %d singular or non-finite line factorisations", *bad);
   return 0;
 }
 
