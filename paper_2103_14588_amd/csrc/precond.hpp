@@ -214,21 +214,27 @@ static int build_line_tables(const dirac_st_problem *p, const LineLayout &L, con
     add(L.f32[a], f32.data(), e * 8);
     add(L.fi32[a], fi32.data(), e * 8);
   }
+  // the pieces fill two contiguous ranges of the workspace layout, the
+  // tables before the factors [0, fac) and the DFT matrices [f64[2], total):
+  // the host block is an image of both, uploaded in (at most) two copies
+  const size_t r1 = L.fac, r2b = p->d >= 2 ? L.f64[2] : L.total, r2 = L.total - r2b;
   auto T = std::make_shared<LineTables>();
-  size_t total = 0;
-  for (auto &pt : parts) total += align256(pt.second.size());
-  if (hipHostMalloc((void **)&T->host, total > 0 ? total : 1, hipHostMallocDefault) == hipSuccess) {
+  const size_t total = r1 + r2;
+  if (hipHostMalloc((void **)&T->host, total, hipHostMallocDefault) == hipSuccess) {
     T->pinned = true;
   } else {
     (void)hipGetLastError();  // handled: the tables live in pageable memory instead
-    T->host = new unsigned char[total > 0 ? total : 1];
+    T->host = new unsigned char[total];
   }
-  size_t h = 0;
+  memset(T->host, 0, total);
   for (auto &pt : parts) {
-    memcpy(T->host + h, pt.second.data(), pt.second.size());
-    T->pieces.push_back({pt.first, h, pt.second.size()});
-    h += align256(pt.second.size());
+    const size_t at = pt.first < r1 ? pt.first : r1 + (pt.first - r2b);
+    DST_CHECK(pt.first + pt.second.size() <= (pt.first < r1 ? r1 : L.total) && (pt.first < r1 || pt.first >= r2b),
+              "line preconditioner table outside its workspace range");
+    memcpy(T->host + at, pt.second.data(), pt.second.size());
   }
+  T->pieces.push_back({0, 0, r1});
+  if (r2 > 0) T->pieces.push_back({r2b, r1, r2});
   out = std::move(T);
   return 0;
 }
