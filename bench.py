@@ -575,6 +575,9 @@ def main():
                      "writes": "complex128 and complex64 blocks, pattern, node-block inverses in both "
                                "precisions, right-hand side (the full operator, isolated launches)"},
         "memory_GB": round((op.bytes() + op64.bytes() + work.numel()) / 1e9, 3),
+        "paper_context": "the paper prints no runtime: its scaling runs timed 100 GMRES iterations "
+                         "(2+1D up to 128^3) with PETSc on dual-socket 18-core Intel Broadwell E5-2695 v4 "
+                         "nodes, 32 MPI ranks per node; the same window here is solve.plain_bj_100it_ms",
     }
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(wl, [x32.cpu().numpy(), x64.cpu().numpy()])
