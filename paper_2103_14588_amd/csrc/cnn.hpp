@@ -12,11 +12,12 @@
 // voxels (one MFMA row tile) and 16 output channels the K dimension runs over
 // (tap, input channel), 32 at a time.  A persistent workgroup walks 4 x 4 x 16
 // voxel tiles (one tau slice per wavefront, one y-row of 16 x per MFMA tile)
-// with the 6 x 6 x 18 halo double-buffered in LDS in a conflict-free
-// chunk-planar layout, and stores through a per-wavefront LDS transpose.
+// with the 6 x 6 x 18 halo double-buffered in LDS in a chunk-planar layout
+// (16 lanes read 128 contiguous bytes), and stores through a per-wavefront
+// LDS transpose.
 // Backward data is the same kernel with the taps flipped and cin/cout swapped;
-// backward weights is an MFMA reduction over voxels (K = voxels,
-// v_mfma_f32_16x16x16_bf16).
+// backward weights is an MFMA reduction over voxels (K = voxels, 32 at a time)
+// from channel-major, x-shifted LDS copies of its operands.
 #pragma once
 
 #include <cstdint>
@@ -25,7 +26,6 @@
 
 namespace dst {
 
-typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 constexpr int kNnParams = 17332;
@@ -117,8 +117,8 @@ __device__ __forceinline__ unsigned halo_fetch(const Grid3 &g, int tile, const u
 // of 4 channels (8 bytes) are planes of HX voxels,
 //   element offset (((a HY + b) CIN / 4 + q) HX + c) 4,
 // so 16 lanes reading one chunk of 16 consecutive voxels read 128 contiguous
-// bytes (no bank conflicts) and every operand address is a per-lane base plus
-// a constant.  (For CIN = 4 this is the plain [a][b][c][4] order.)
+// bytes (one pass over the banks) and every operand address is a per-lane
+// base plus a constant.  (For CIN = 4 this is the plain [a][b][c][4] order.)
 template <int CIN>
 __device__ __forceinline__ int halo_off(int a, int b, int q, int c) {
   return (((a * HY + b) * (CIN / 4) + q) * HX + c) * 4;
