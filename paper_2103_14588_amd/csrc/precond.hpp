@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -57,6 +58,9 @@ struct Precond {
   const dirac_st_nn *nn = nullptr;
   bool nn_on = false;
   unsigned char *nnwork = nullptr;
+  // spectral: the pivot inverses are computed by the first application after
+  // the set-up (inside its block elimination) rather than by a pass of their own
+  mutable bool piv_pending = false;
 };
 
 static void spec_geom(const dirac_st_problem *p, double vbar, SpecGeom &G) {
@@ -376,16 +380,7 @@ static int pc_setup(Precond &P, const dirac_st_bsr *A, int kind, double vbar, un
   P.SL = spec_layout(&A->prob, P.prec);
   spec_geom(&A->prob, vbar, P.G);
   if (int rc = spec_twiddles(P.G, spec, P.SL, s)) return rc;
-  const unsigned g = (unsigned)((P.G.S + 63) / 64);
-  const double2 *tw64 = (const double2 *)(spec + P.SL.tw64);
-  cx<T> *piv = (cx<T> *)(spec + P.SL.piv);
-  if (A->prob.d == 1)
-    spectral_setup<T, 2, 1><<<g, 64, 0, s>>>(P.G, tw64, piv);
-  else if (A->prob.d == 2)
-    spectral_setup<T, 2, 2><<<g, 64, 0, s>>>(P.G, tw64, piv);
-  else
-    spectral_setup<T, 4, 3><<<g, 64, 0, s>>>(P.G, tw64, piv);
-  DST_LAUNCHED();
+  P.piv_pending = true;
   return 0;
 }
 
@@ -421,13 +416,22 @@ static int pc_apply_base(const Precond &P, const cx<T> *v, cx<T> *z, double scal
       if (pass == 0) {
         const unsigned g = (unsigned)((G.S + 63) / 64);
         const double2 *tw64 = (const double2 *)(P.spec + P.SL.tw64);
-        const cx<T> *piv = (const cx<T> *)(P.spec + P.SL.piv);
-        if (G.d == 1)
-          spectral_thomas<T, 2, 1><<<g, 64, 0, s>>>(G, tw64, piv, z);
-        else if (G.d == 2)
-          spectral_thomas<T, 2, 2><<<g, 64, 0, s>>>(G, tw64, piv, z);
-        else
-          spectral_thomas<T, 4, 3><<<g, 64, 0, s>>>(G, tw64, piv, z);
+        cx<T> *piv = (cx<T> *)(P.spec + P.SL.piv);
+        auto thomas = [&](auto setup) {
+          constexpr bool SU = decltype(setup)::value;
+          if (G.d == 1)
+            spectral_thomas<T, 2, 1, SU><<<g, 64, 0, s>>>(G, tw64, piv, z);
+          else if (G.d == 2)
+            spectral_thomas<T, 2, 2, SU><<<g, 64, 0, s>>>(G, tw64, piv, z);
+          else
+            spectral_thomas<T, 4, 3, SU><<<g, 64, 0, s>>>(G, tw64, piv, z);
+        };
+        if (P.piv_pending) {
+          thomas(std::true_type{});
+          P.piv_pending = false;
+        } else {
+          thomas(std::false_type{});
+        }
         DST_LAUNCHED();
       }
     }

@@ -165,41 +165,19 @@ __device__ inline void inverse_nc(const double2 *a, double2 *inv) {
     for (int j = 0; j < NC; j++) inv[i * NC + j] = m[i][NC + j];
 }
 
-// Pivot inverses of the block elimination along time, one thread per mode.
-template <typename T, int NC, int DS>
-__global__ __launch_bounds__(64) void spectral_setup(SpecGeom G, const double2 *__restrict__ tw,
-                                                     cx<T> *__restrict__ piv) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= G.S) return;
-  double2 L[NC * NC], U[NC * NC], Di[NC * NC], Dl[NC * NC], P[NC * NC], Pinv[NC * NC],
-      t1[NC * NC], t2[NC * NC];
-  mode_blocks<NC, DS>(G, s, tw, L, U, Di, Dl);
-  for (int tau = 0; tau < G.nt; tau++) {
-    const bool last = (tau == G.nt - 1);
-    if (tau == 0) {
-#pragma unroll
-      for (int q = 0; q < NC * NC; q++) P[q] = last ? Dl[q] : Di[q];
-    } else {
-      matmul_nc<NC>(L, Pinv, t1);
-      matmul_nc<NC>(t1, U, t2);
-#pragma unroll
-      for (int q = 0; q < NC * NC; q++) P[q] = csub(last ? Dl[q] : Di[q], t2[q]);
-    }
-    inverse_nc<NC>(P, Pinv);
-    cx<T> *o = piv + ((int64_t)tau * G.S + s) * NC * NC;
-#pragma unroll
-    for (int q = 0; q < NC * NC; q++) o[q] = mk<cx<T>>((T)Pinv[q].x, (T)Pinv[q].y);
-  }
-}
-
 // Block elimination along time for every mode, in place on data
 // ([nt][S][NC] in the spatial-frequency domain).  One thread per mode; the
 // time loop is cut into batches of PF steps whose loads (right-hand side rows
 // and pivot inverses) are all issued before the batch's dependent arithmetic,
 // so PF memory latencies overlap.
-template <typename T, int NC, int DS>
+//
+// SETUP: the first application after a set-up also computes the pivot
+// inverses, P_0 = D, P_tau = D - L P_{tau-1}^{-1} U (the last row with its own
+// diagonal block), in FP64 during the forward sweep, stores them rounded to T
+// and uses the rounded values exactly as a later application reads them back.
+template <typename T, int NC, int DS, bool SETUP>
 __global__ __launch_bounds__(64) void spectral_thomas(SpecGeom G, const double2 *__restrict__ tw,
-                                                      const cx<T> *__restrict__ piv,
+                                                      cx<T> *__restrict__ piv,
                                                       cx<T> *__restrict__ data) {
   using C = cx<T>;
   constexpr int PF = (NC == 2) ? 8 : (sizeof(T) == 4 ? 2 : 1);
@@ -216,9 +194,66 @@ __global__ __launch_bounds__(64) void spectral_thomas(SpecGeom G, const double2 
   const int nt = G.nt;
   const int64_t rs = G.S * NC, ps = G.S * NC * NC;
   C *col = data + s * NC;
-  const C *pcol = piv + s * NC * NC;
+  C *pcol = piv + s * NC * NC;
   // forward: y_tau = r_tau - L P^{-1}_{tau-1} y_{tau-1}
   C prev[NC];
+  if constexpr (SETUP) {
+    double2 Pinv[NC * NC];  // P^{-1}_{tau-1} in FP64 (the recurrence)
+    C pprev[NC * NC];       // the same rounded to T (what the sweep uses)
+    for (int t0 = 0; t0 < nt; t0 += PF) {
+      C rb[PF][NC];
+#pragma unroll
+      for (int u = 0; u < PF; u++) {
+        const int tau = t0 + u;
+        if (tau < nt) {
+#pragma unroll
+          for (int i = 0; i < NC; i++) rb[u][i] = col[tau * rs + i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PF; u++) {
+        const int tau = t0 + u;
+        if (tau < nt) {
+          const bool last = (tau == nt - 1);
+          double2 P[NC * NC], t1[NC * NC], t2[NC * NC], Pn[NC * NC];
+          if (tau == 0) {
+#pragma unroll
+            for (int q = 0; q < NC * NC; q++) P[q] = last ? Dl[q] : Di[q];
+          } else {
+            matmul_nc<NC>(L64, Pinv, t1);
+            matmul_nc<NC>(t1, U64, t2);
+#pragma unroll
+            for (int q = 0; q < NC * NC; q++) P[q] = csub(last ? Dl[q] : Di[q], t2[q]);
+          }
+          inverse_nc<NC>(P, Pn);
+          if (tau > 0) {
+            C z[NC];
+#pragma unroll
+            for (int i = 0; i < NC; i++) {
+              z[i] = mk<C>(0, 0);
+#pragma unroll
+              for (int j = 0; j < NC; j++) z[i] = cfma(z[i], pprev[i * NC + j], prev[j]);
+            }
+#pragma unroll
+            for (int i = 0; i < NC; i++)
+#pragma unroll
+              for (int j = 0; j < NC; j++) rb[u][i] = cfms(rb[u][i], Lm[i * NC + j], z[j]);
+          }
+#pragma unroll
+          for (int i = 0; i < NC; i++) {
+            col[tau * rs + i] = rb[u][i];
+            prev[i] = rb[u][i];
+          }
+#pragma unroll
+          for (int q = 0; q < NC * NC; q++) {
+            Pinv[q] = Pn[q];
+            pprev[q] = mk<C>((T)Pn[q].x, (T)Pn[q].y);
+            pcol[tau * ps + q] = pprev[q];
+          }
+        }
+      }
+    }
+  } else {
   for (int t0 = 0; t0 < nt; t0 += PF) {
     C rb[PF][NC], pb[PF][NC * NC];
 #pragma unroll
@@ -257,6 +292,7 @@ __global__ __launch_bounds__(64) void spectral_thomas(SpecGeom G, const double2 
         }
       }
     }
+  }
   }
   // backward: x_tau = P^{-1}_tau (y_tau - U x_{tau+1})
   for (int t0 = nt - 1; t0 >= 0; t0 -= PF) {
