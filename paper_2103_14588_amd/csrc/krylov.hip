@@ -49,9 +49,28 @@ __global__ __launch_bounds__(256) void norm_pass(const cx<T> *__restrict__ w,
     partial[blockIdx.x] = mk<double2>(red[0] + red[1] + red[2] + red[3], 0.0);
 }
 
-// ctrl->est_abs = ctrl->dots_norm2 (parks a norm^2 so a second one can follow)
-static __global__ void copy_norm_to_est(Ctrl *ctrl) {
-  if (threadIdx.x == 0) ctrl->est_abs = ctrl->dots_norm2;
+// ||x||^2 and ||b||^2 in one pass: partial[b] = (block sum |x|^2, block sum |b|^2),
+// each component summed exactly as norm_pass sums it
+__global__ __launch_bounds__(256) void norm_pass2(const double2 *__restrict__ x, const double2 *__restrict__ b,
+                                                  double2 *__restrict__ partial, int64_t n) {
+  __shared__ double red[2][4];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double sx = 0.0, sb = 0.0;
+  if (e < n) {
+    const double2 vx = x[e], vb = b[e];
+    sx = vx.x * vx.x + vx.y * vx.y;
+    sb = vb.x * vb.x + vb.y * vb.y;
+  }
+  sx = wave_sum(sx);
+  sb = wave_sum(sb);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sx;
+    red[1][threadIdx.x >> 6] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[blockIdx.x] = mk<double2>(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                                      red[1][0] + red[1][1] + red[1][2] + red[1][3]);
 }
 
 __global__ __launch_bounds__(256) void zero_c128(double2 *x, int64_t n) {
@@ -225,11 +244,8 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   // which the control block keeps two doubles apart)
   double xnorm = 0.0, bnorm = 0.0;
   {
-    norm_pass<double><<<nblocks(N), 256, 0, s>>>(x, partial, N);
-    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
-    copy_norm_to_est<<<1, 64, 0, s>>>(ctrl);
-    norm_pass<double><<<nblocks(N), 256, 0, s>>>(b, partial, N);
-    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
+    norm_pass2<<<nblocks(N), 256, 0, s>>>(x, b, partial, N);
+    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 2, 0);
     DST_LAUNCHED();
     static_assert(offsetof(Ctrl, est_abs) == offsetof(Ctrl, dots_norm2) + 2 * sizeof(double),
                   "norm^2 and estimate slots");

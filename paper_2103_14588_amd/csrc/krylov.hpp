@@ -180,6 +180,7 @@ __global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int
 // Layout: partial[k * nblk + b], contiguous per coefficient.
 // what: 0 -> Gram-Schmidt coefficients into dst (h1 or h2) and coef = sigma_k h_k
 //       1 -> norm^2 into ctrl->dots_norm2
+//       2 -> a pair of norms^2: first into ctrl->est_abs, second into ctrl->dots_norm2
 __device__ __forceinline__ void reduce_coef(int k, const double2 *__restrict__ partial, int64_t nblk,
                                    Ctrl *__restrict__ ctrl, int what, int which) {
   __shared__ double sx[4], sy[4];
@@ -214,6 +215,9 @@ __device__ __forceinline__ void reduce_coef(int k, const double2 *__restrict__ p
     double x = sx[0] + sx[1] + sx[2] + sx[3], y = sy[0] + sy[1] + sy[2] + sy[3];
     if (what == 1) {
       ctrl->dots_norm2 = x;
+    } else if (what == 2) {
+      ctrl->est_abs = x;
+      ctrl->dots_norm2 = y;
     } else {
       const double s = ctrl->sigma[k];
       double2 h = mk<double2>(x * s, y * s);  // true basis vector k = sigma_k * stored
