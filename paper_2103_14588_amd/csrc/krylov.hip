@@ -243,10 +243,15 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   // ||b||^2 come back in one copy (the estimate slot and the norm^2 slot,
   // which the control block keeps two doubles apart)
   double xnorm = 0.0, bnorm = 0.0;
+  double2 *rbuf = sizeof(T) == 8 ? (double2 *)V : r64;
   {
     norm_pass2<<<nblocks(N), 256, 0, s>>>(x, b, partial, N);
     reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 2, 0);
     DST_LAUNCHED();
+    // the residual of a zero initial guess is b: the copy is queued before the
+    // norms are read back, so it runs while the host waits (with a nonzero x
+    // the first residual product overwrites it)
+    DST_HIP(hipMemcpyAsync(rbuf, b, (size_t)N * sizeof(double2), hipMemcpyDeviceToDevice, s));
     static_assert(offsetof(Ctrl, est_abs) == offsetof(Ctrl, dots_norm2) + 2 * sizeof(double),
                   "norm^2 and estimate slots");
     DST_HIP(hipMemcpyAsync(hrb, &ctrl->dots_norm2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -267,13 +272,11 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
     return DIRAC_ST_OK;
   }
   int its = 0, rc_final = DIRAC_ST_NOT_CONVERGED;
-  double2 *rbuf = sizeof(T) == 8 ? (double2 *)V : r64;
   for (;;) {
     // true residual in FP64
     double rn = 0.0;
     if (x_zero) {
-      DST_HIP(hipMemcpyAsync(rbuf, b, (size_t)N * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      rn = bnorm;
+      rn = bnorm;  // rbuf already holds b
       x_zero = false;
     } else {
       DST_HIP(apply_op<double>(A, mf, A->val64, x, b, rbuf, 1.0, true, s));
