@@ -449,6 +449,11 @@ def main():
     # plain GMRES(50) with node-block Jacobi: the 100-iteration window
     obj = D.make_opts(restart=m, max_it=100, pc="bj", precision=64, rtol=rtol)
     ms_bj, info_bj = solve(obj)
+    # the same 100-iteration window with FP32-IR (complex64 inner cycles): the
+    # regime where iterations dominate and the reduced precision pays
+    obj32 = D.make_opts(restart=m, max_it=100, pc="bj", precision=32, rtol=rtol, inner_rtol=1e-4)
+    solve(obj32)
+    ms_bj32, info_bj32 = solve(obj32)
 
     # BiCGSTAB (the paper's second solver): with the step's preconditioner, and
     # the 100-iteration window with node-block Jacobi
@@ -532,6 +537,10 @@ def main():
             "step_relres": info_step["relres"], "step_iters": info_step["iters"],
             "plain_bj_100it_ms": round(ms_bj, 3), "plain_bj_100it_relres": info_bj["relres"],
             "plain_bj_ms_per_iter": round(ms_bj / max(info_bj["iters"], 1), 4),
+            "fp32_ir_bj_100it_ms": round(ms_bj32, 3), "fp32_ir_bj_100it_relres": info_bj32["relres"],
+            "fp32_ir_bj_ms_per_iter": round(ms_bj32 / max(info_bj32["iters"], 1), 4),
+            "speedup_fp32ir_vs_fp64_per_iter_bj": round((ms_bj / max(info_bj["iters"], 1))
+                                                        / (ms_bj32 / max(info_bj32["iters"], 1)), 3),
             "fp64_matrix_free_ms": round(ms_mf, 3), "fp64_matrix_free_iters": info_mf["iters"],
             "fp64_matrix_free_relres": info_mf["relres"],
             "bicgstab_ms": round(ms_bi, 3), "bicgstab_iters": info_bi["iters"],
