@@ -165,3 +165,26 @@ def test_line_pc_staged_single_system(D):
         z = D.pc_apply(op, v, pc="line").to(torch.complex128)
         r = D.spmv(op, z) - b
         assert float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)) <= tol, ctype
+
+
+def test_line_tables_of_similar_problems_stay_apart(D):
+    """The host tables of the line preconditioner are kept per problem: two
+    problems that share the mesh and lengths but differ in the potential (step
+    height and position, and a potential-free one), applied alternately and
+    twice each through one shared workspace, each give their own exact
+    inverse, in both precisions."""
+    specs = [IN.Spec(d=2, n=[5, 12, 11], vkind=1, v0=2.5, x0=0.5),
+             IN.Spec(d=2, n=[5, 12, 11], vkind=1, v0=1.0, x0=0.3),
+             IN.Spec(d=2, n=[5, 12, 11])]
+    ops = [D.assemble(s, None)[0] for s in specs]
+    dense = [O.Matrix(oprob(s)).dense() for s in specs]
+    v = rand_c(ops[0].n, 7)
+    work = torch.empty(16 << 20, dtype=torch.uint8, device="cuda")  # ample for these meshes
+    for _ in range(2):
+        for op, Ad in zip(ops, dense):
+            want = np.linalg.solve(Ad, v)
+            z = host(D.pc_apply(op, dev(v), pc="line", work=work))
+            assert np.linalg.norm(z - want) <= 1e-10 * np.linalg.norm(want)
+            want32 = np.linalg.solve(Ad, v.astype(np.complex64).astype(np.complex128))
+            z32 = host(D.pc_apply(op, dev(v.astype(np.complex64)), pc="line", work=work)).astype(np.complex128)
+            assert np.linalg.norm(z32 - want32) <= 2e-4 * np.linalg.norm(want32)
