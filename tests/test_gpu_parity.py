@@ -185,6 +185,7 @@ def test_gmres_solution_matches_exact(D, spec, precision):
 @pytest.mark.parametrize("spec", [
     IN.Spec(d=2, n=[6, 17, 9], lens=[1.0, 0.9, 1.1], vkind=1, v0=2.5, x0=0.5),
     IN.Spec(d=1, n=[7, 37], lens=[0.8, 1.3]),
+    IN.Spec(d=3, n=[3, 4, 5, 3], vkind=1, v0=1.0, x0=0.4),
 ], ids=ids)
 def test_complex128_only_assembly(D, spec):
     """Assembly without the complex64 copy and the node-block inverses (all a
@@ -251,6 +252,27 @@ def test_gmres_edge_cases(D):
     # max_it reached -> NOT_CONVERGED with valid stats
     x, info = D.gmres(op, b, restart=5, max_it=3, rtol=1e-15, pc="bj")
     assert info["rc"] == D.NOT_CONVERGED and info["iters"] == 3 and np.isfinite(info["relres"])
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_gmres_nonzero_initial_guess(D, precision):
+    """A nonzero initial guess: started from the solution GMRES stops before
+    its first Arnoldi step with x unchanged; started from a random vector it
+    lands on the same solution (the first residual is b - A x0, not b)."""
+    spec = IN.Spec(d=2, n=[5, 12, 11], vkind=1, v0=2.5, x0=0.5)
+    psi0 = rand_c(spec.spatial * spec.nc, 9)
+    op, b = D.assemble(spec, dev(psi0))
+    A_or = O.Matrix(oprob(spec))
+    x_ref = np.linalg.solve(A_or.dense(), A_or.rhs(psi0))
+    kw = dict(restart=20, max_it=400, rtol=1e-10, pc="spectral", vbar=1.25, precision=precision,
+              inner_rtol=1e-4 if precision == 32 else 0.0)
+    x0 = dev(x_ref.copy())
+    x, info = D.gmres(op, b, x=x0.clone(), **kw)
+    assert info["converged"] and info["iters"] == 0, info
+    assert torch.equal(x, x0)
+    x, info = D.gmres(op, b, x=dev(rand_c(op.n, 10)), **kw)
+    assert info["converged"], info
+    assert np.linalg.norm(host(x) - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
 
 
 # ---------------------------------------------------- full-size, sampled
