@@ -106,10 +106,101 @@ inline LineLayout line_layout(const dirac_st_problem *p, int prec, int slabs = 1
 // 64 x 64 output tile per workgroup, 4 x 4 per thread (rows ty + 16 i,
 // columns tx + 16 j, so that global accesses are coalesced), K in steps of
 // 16 through LDS.
+// Complex128: the same tile on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+// Real and imaginary parts are staged as separate LDS planes; wavefront w owns
+// the 32 x 32 quarter (rows 32 (w >> 1), columns 32 (w & 1)) as 2 x 2 blocks
+// of 16 x 16, each a complex product from four real ones
+//   Yr += Ar Xr - Ai Xi,  Yi += Ar Xi + Ai Xr.
+// Operands: lane l holds A[m = l % 16][k = l / 16] and X[k = l / 16][n = l % 16];
+// result register q of lane l is D[l / 16 + 4 q][l % 16] (the FP64 form
+// interleaves the rows: measured on gfx950).  Per k step of 4 a wavefront reads
+// 8 doubles per lane from LDS for 16 MFMAs (8 flops per byte, against 1 for
+// the vector-FMA tile, whose LDS reads bound it).
+typedef double d4v_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void tgemm_tile_f64(const double2 *__restrict__ A, int pk,
+                                               const double2 *__restrict__ X, double2 *__restrict__ Y, int n,
+                                               int64_t ncol, int row0, int64_t col0, double scale) {
+  constexpr int LP = 64 + 2;  // plane row length (doubles), padded
+  __shared__ double Ar[16][LP], Ai[16][LP], Xr[16][LP], Xi[16][LP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb = 32 * (wave >> 1), cb = 32 * (wave & 1);
+  const int m = lane & 15, kq = lane >> 4;
+  d4v_t accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) accR[i][j] = accI[i][j] = d4v_t{0.0, 0.0, 0.0, 0.0};
+  // the next K block of A and X is fetched into registers while the current
+  // block's MFMAs run
+  double2 pa[4], px[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int e = threadIdx.x + 256 * q;
+      pa[q] = A[(int64_t)(row0 + (e >> 4)) * pk + k0 + (e & 15)];
+      const int k = k0 + (e >> 6);
+      const int64_t col = col0 + (e & 63);
+      px[q] = (k < n && col < ncol) ? X[(int64_t)k * ncol + col] : mk<double2>(0, 0);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < n; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int e = threadIdx.x + 256 * q;
+      Ar[e & 15][e >> 4] = pa[q].x;
+      Ai[e & 15][e >> 4] = pa[q].y;
+      Xr[e >> 6][e & 63] = px[q].x;
+      Xi[e >> 6][e & 63] = px[q].y;
+    }
+    __syncthreads();
+    if (k0 + 16 < n) fetch(k0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      const int kk = ks + kq;
+      double ar[2], ai[2], xr[2], xi[2];
+#pragma unroll
+      for (int i = 0; i < 2; i++) {
+        ar[i] = Ar[kk][rb + 16 * i + m];
+        ai[i] = Ai[kk][rb + 16 * i + m];
+        xr[i] = Xr[kk][cb + 16 * i + m];
+        xi[i] = Xi[kk][cb + 16 * i + m];
+      }
+      // the eight accumulators first take their ar terms, then their ai
+      // terms, so that no MFMA waits on the one issued just before it
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], xr[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], xi[j], accI[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], xi[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], xr[j], accI[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int r = row0 + rb + 16 * i + kq + 4 * q;
+        const int64_t c = col0 + cb + 16 * j + m;
+        if (r < n && c < ncol) Y[(int64_t)r * ncol + c] = mk<double2>(accR[i][j][q] * scale, accI[i][j][q] * scale);
+      }
+}
+
 template <typename T>
-__device__ __forceinline__ void tgemm_tile(const cx<T> *__restrict__ A, int pk, const cx<T> *__restrict__ X,
-                                  cx<T> *__restrict__ Y, int n, int64_t ncol, int row0, int64_t col0,
-                                  T scale) {
+__device__ __forceinline__ void tgemm_tile_fma(const cx<T> *__restrict__ A, int pk, const cx<T> *__restrict__ X,
+                                               cx<T> *__restrict__ Y, int n, int64_t ncol, int row0, int64_t col0,
+                                               T scale) {
   using C = cx<T>;
   __shared__ C As[16][64];
   __shared__ C Bs[16][64];
@@ -159,6 +250,17 @@ __device__ __forceinline__ void tgemm_tile(const cx<T> *__restrict__ A, int pk, 
       if (c < ncol) Y[(int64_t)r * ncol + c] = mk<C>(acc[i][j].x * scale, acc[i][j].y * scale);
     }
   }
+}
+
+// complex128 on the matrix cores, complex64 with vector FMAs
+template <typename T>
+__device__ __forceinline__ void tgemm_tile(const cx<T> *__restrict__ A, int pk, const cx<T> *__restrict__ X,
+                                  cx<T> *__restrict__ Y, int n, int64_t ncol, int row0, int64_t col0,
+                                  T scale) {
+  if constexpr (sizeof(T) == 8)
+    tgemm_tile_f64(A, pk, X, Y, n, ncol, row0, col0, scale);
+  else
+    tgemm_tile_fma<T>(A, pk, X, Y, n, ncol, row0, col0, scale);
 }
 
 // grid: (column tiles, row tiles, batches); batch b works on X + b n ncol
