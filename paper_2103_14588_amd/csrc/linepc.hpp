@@ -565,6 +565,116 @@ __device__ __forceinline__ void line_solve_thread(const cx<T> *__restrict__ fac,
   }
 }
 
+// The same solve for 2 x 2 blocks with the node loads issued PF nodes at a
+// time: every sweep loads the factors and values of the next PF nodes before
+// their dependent arithmetic, so PF memory latencies overlap instead of one
+// (the kernel runs one thread per line and about one wavefront per compute
+// unit, so latency, not bandwidth, is what bounds it).  The correction sweep
+// has no dependency between nodes at all.
+template <typename T, int PF>
+__device__ __forceinline__ void line_solve_thread2(const cx<T> *__restrict__ fac, const cx<T> *__restrict__ lined,
+                                                cx<T> *__restrict__ X, int n1, int64_t lines, int64_t l) {
+  constexpr int NC = 2, B = NC * NC;
+  using C = cx<T>;
+  C *x = X + l * n1 * NC;
+  auto fb = [&](int i, int slot) { return ((int64_t)i * 4 * B + slot * B) * lines + l; };
+  C y[NC], t[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) y[c] = mk<C>(0, 0);
+  // forward: y_i = G_i v_i - K_i y_{i-1}
+  for (int i0 = 0; i0 < n1 - 1; i0 += PF) {
+    C Gb[PF][B], Kb[PF][B], vb[PF][NC];
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int i = i0 + u;
+      if (i < n1 - 1) {
+        blk_load<T, NC>(fac, fb(i, 0), lines, Gb[u]);
+        blk_load<T, NC>(fac, fb(i, 1), lines, Kb[u]);
+#pragma unroll
+        for (int c = 0; c < NC; c++) vb[u][c] = x[i * NC + c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int i = i0 + u;
+      if (i < n1 - 1) {
+        blk_apply<T, NC>(Gb[u], vb[u], t, false, false);
+        blk_apply<T, NC>(Kb[u], y, t, true, true);
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+          y[c] = t[c];
+          x[i * NC + c] = t[c];
+        }
+      }
+    }
+  }
+  // backward: a_i = y_i - E_i a_{i+1}, from a_{n-2} = y_{n-2}
+  C alast[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) alast[c] = y[c];
+  for (int i0 = n1 - 3; i0 >= 0; i0 -= PF) {
+    C Eb[PF][B], vb[PF][NC];
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int i = i0 - u;
+      if (i >= 0) {
+        blk_load<T, NC>(fac, fb(i, 2), lines, Eb[u]);
+#pragma unroll
+        for (int c = 0; c < NC; c++) vb[u][c] = x[i * NC + c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int i = i0 - u;
+      if (i >= 0) {
+#pragma unroll
+        for (int c = 0; c < NC; c++) t[c] = vb[u][c];
+        blk_apply<T, NC>(Eb[u], y, t, true, true);
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+          y[c] = t[c];
+          x[i * NC + c] = t[c];
+        }
+      }
+    }
+  }
+  // last node: S^{-1} (v_{n-1} - L_{n-1} a_{n-2} - U_{n-1} a_0)
+  C Mq[B];
+#pragma unroll
+  for (int c = 0; c < NC; c++) t[c] = x[(n1 - 1) * NC + c];
+  blk_load<T, NC>(lined, 0 * B * lines + l, lines, Mq);
+  blk_apply<T, NC>(Mq, alast, t, true, true);
+  blk_load<T, NC>(lined, 1 * B * lines + l, lines, Mq);
+  blk_apply<T, NC>(Mq, y, t, true, true);
+  C xl[NC];
+  blk_load<T, NC>(lined, 2 * B * lines + l, lines, Mq);
+  blk_apply<T, NC>(Mq, t, xl, false, false);
+#pragma unroll
+  for (int c = 0; c < NC; c++) x[(n1 - 1) * NC + c] = xl[c];
+  // x_i = a_i + H_i x_{n-1}
+  for (int i0 = 0; i0 < n1 - 1; i0 += PF) {
+    C Hb[PF][B], vb[PF][NC];
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int i = i0 + u;
+      if (i < n1 - 1) {
+        blk_load<T, NC>(fac, fb(i, 3), lines, Hb[u]);
+#pragma unroll
+        for (int c = 0; c < NC; c++) vb[u][c] = x[i * NC + c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+      const int i = i0 + u;
+      if (i < n1 - 1) {
+        blk_apply<T, NC>(Hb[u], xl, vb[u], true, false);
+#pragma unroll
+        for (int c = 0; c < NC; c++) x[i * NC + c] = vb[u][c];
+      }
+    }
+  }
+}
+
 // In-place periodic block-tridiagonal solve along x for the 64 lines
 // l0 .. l0 + 63 of one workgroup (line l holds nodes l * n1 .. l * n1 + n1 - 1,
 // nc components each); thread t owns line l0 + t.  The line values move
@@ -699,6 +809,7 @@ __device__ __forceinline__ void line_solve_wg(const cx<T> *__restrict__ fac, con
 
 // chunk length of the LDS-staged line solve (nodes)
 constexpr int kLineChunk = 8;
+constexpr int kLinePF = 8;  // nodes per load round of the one-thread-per-line solve (2 x 2 blocks)
 
 template <typename T, int NC>
 __global__ __launch_bounds__(64) void line_solve(const cx<T> *__restrict__ fac,
@@ -712,7 +823,9 @@ __global__ __launch_bounds__(64) void line_solve_pt(const cx<T> *__restrict__ fa
                                                     const cx<T> *__restrict__ lined,
                                                     cx<T> *__restrict__ X, int n1, int64_t lines) {
   const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (l < lines) line_solve_thread<T, NC>(fac, lined, X, n1, lines, l);
+  if (l >= lines) return;
+  if constexpr (NC == 2) line_solve_thread2<T, kLinePF>(fac, lined, X, n1, lines, l);
+  else line_solve_thread<T, NC>(fac, lined, X, n1, lines, l);
 }
 
 // below this many lines a single system's solve runs one thread per line
