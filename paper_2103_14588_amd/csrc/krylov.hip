@@ -78,13 +78,27 @@ __global__ __launch_bounds__(256) void zero_c128(double2 *x, int64_t n) {
   if (e < n) x[e] = mk<double2>(0, 0);
 }
 
-static int maxk_bucket(int jp1) { return jp1 <= 8 ? 8 : jp1 <= 16 ? 16 : jp1 <= 32 ? 32 : 64; }
+static int maxk_bucket(int jp1) {
+  return jp1 <= 1 ? 1 : jp1 <= 2 ? 2 : jp1 <= 4 ? 4 : jp1 <= 8 ? 8 : jp1 <= 16 ? 16 : jp1 <= 32 ? 32 : 64;
+}
+
+// Passes over at most four basis vectors move too few bytes per thread to
+// keep the memory system busy with one element each: their threads take four.
+constexpr int kSmallSetEpt = 4;
+static int64_t pass_blocks(int64_t n, int mk) {
+  const int64_t per = 256 * (mk <= 4 ? kSmallSetEpt : 1);
+  return (n + per - 1) / per;
+}
 
 template <typename T, int MODE>
 static hipError_t launch_pass_mk(int mk, const cx<T> *V, int64_t ldv, int jp1, cx<T> *w,
                                  const double2 *coef, double2 *partial, int64_t n, hipStream_t s) {
-  const unsigned g = nblocks(n);
+  const unsigned g = (unsigned)pass_blocks(n, mk);
+  constexpr int E = kSmallSetEpt;
   switch (mk) {
+    case 1: cgs_pass<T, 1, MODE, E><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    case 2: cgs_pass<T, 2, MODE, E><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
+    case 4: cgs_pass<T, 4, MODE, E><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
     case 8: cgs_pass<T, 8, MODE><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
     case 16: cgs_pass<T, 16, MODE><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
     case 32: cgs_pass<T, 32, MODE><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
@@ -103,14 +117,7 @@ static bool fused_updots_ok(int) {
 template <typename T>
 static hipError_t launch_updots(int mk, const cx<T> *V, int64_t ldv, int jp1, cx<T> *w,
                                 const double2 *coef, double2 *partial, int64_t n, hipStream_t s) {
-  const unsigned g = nblocks(n);
-  switch (mk) {
-    case 8: cgs_pass<T, 8, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
-    case 16: cgs_pass<T, 16, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
-    case 32: cgs_pass<T, 32, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
-    default: cgs_pass<T, 64, UPDOTS><<<g, 256, 0, s>>>(V, ldv, jp1, w, coef, partial, n); break;
-  }
-  return hipGetLastError();
+  return launch_pass_mk<T, UPDOTS>(mk, V, ldv, jp1, w, coef, partial, n, s);
 }
 
 // ------------------------------------------------------------ layout
@@ -329,9 +336,10 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
         DST_HIP(apply_op<T>(A, mf, val, zj, nullptr, w, (T)1, false, s));
       }
       const int jp1 = j + 1, mk = maxk_bucket(jp1);
+      const int64_t nbk = pass_blocks(N, mk);  // partial sums per coefficient
       // pass 1: h1 = V^H w
       DST_HIP((launch_pass_mk<T, DOTS>(mk, V, L.ldv, jp1, w, nullptr, partial, N, s)));
-      reduce_partials<<<jp1, 256, 0, s>>>(partial, nblk, ctrl, 0, 1);
+      reduce_partials<<<jp1, 256, 0, s>>>(partial, nbk, ctrl, 0, 1);
       DST_LAUNCHED();
       // pass 2: w -= V h1, h2 = V^H w
       if (fused_updots_ok<T>(mk)) {
@@ -340,11 +348,11 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
         DST_HIP((launch_pass_mk<T, UPDATE>(mk, V, L.ldv, jp1, w, ctrl->coef, partial, N, s)));
         DST_HIP((launch_pass_mk<T, DOTS>(mk, V, L.ldv, jp1, w, nullptr, partial, N, s)));
       }
-      reduce_partials<<<jp1, 256, 0, s>>>(partial, nblk, ctrl, 0, 2);
+      reduce_partials<<<jp1, 256, 0, s>>>(partial, nbk, ctrl, 0, 2);
       DST_LAUNCHED();
       // pass 3: w -= V h2, ||w||^2
       DST_HIP((launch_pass_mk<T, UPNORM>(mk, V, L.ldv, jp1, w, ctrl->coef, partial, N, s)));
-      reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
+      reduce_partials<<<1, 256, 0, s>>>(partial, nbk, ctrl, 1, 0);
       givens_step<<<1, 64, 0, s>>>(ctrl, j);
       DST_LAUNCHED();
       Readback rb{};

@@ -62,38 +62,54 @@ __device__ inline S wave_sum(S v) {
 }
 
 // ------------------------------------------------------------ pass kernels
-// One element per thread; block b covers elements [256 b, 256 b + 256).
+// Each thread takes EPT elements: block b covers [256 EPT b, 256 EPT (b + 1)),
+// thread t the elements 256 (EPT b + i) + t, i < EPT.
 // Modes:
 //   DOTS    partial[k][b] = sum_e conj(V_k[e]) w[e], k < jp1   (tiles of 32)
 //   UPDOTS  w[e] -= sum_k V_k[e] coef[k]; partial[k][b] = sum conj(V_k[e]) w_new[e]
 //   UPNORM  w[e] -= sum_k V_k[e] coef[k]; partial[0][b] = sum |w_new[e]|^2
 //   UPDATE  w[e] -= sum_k V_k[e] coef[k]
+// A thread sums its own elements in order before the wavefront butterfly;
+// with EPT = 1 every product enters the butterfly as it is.
 enum PassMode { DOTS = 0, UPDOTS = 1, UPNORM = 2, UPDATE = 3 };
 
-template <typename T, int MAXK, int MODE>
+template <typename T, int MAXK, int MODE, int EPT = 1>
 __device__ __forceinline__ void cgs_block(int64_t blk, int64_t nblk, const cx<T> *__restrict__ V, int64_t ldv, int jp1,
                                                  cx<T> *__restrict__ w,
                                                  const double2 *__restrict__ coef,
                                                  double2 *__restrict__ partial, int64_t n) {
   using C = cx<T>;
-  __shared__ double red[4][(MAXK < 32 ? MAXK : 32)][2];
-  const int64_t e = blk * 256 + threadIdx.x;
-  const bool in = e < n;
+  constexpr int KT = MAXK < 32 ? MAXK : 32;
+  __shared__ double red[4][KT][2];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  C we = in ? w[e] : mk<C>(0, 0);
-  if (MODE == DOTS) {
-    constexpr int KT = MAXK < 32 ? MAXK : 32;
+  int64_t e[EPT];
+  bool in[EPT];
+  C we[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    e[i] = (blk * EPT + i) * 256 + threadIdx.x;
+    in[i] = e[i] < n;
+    we[i] = in[i] ? w[e[i]] : mk<C>(0, 0);
+  }
+  // partial[k][blk] = sum over the block's elements of conj(V_k) x, one
+  // butterfly per tile of basis vectors
+  auto dots = [&](const C(&x)[EPT]) {
 #pragma unroll 1
     for (int t0 = 0; t0 < MAXK; t0 += KT) {
       if (t0 >= jp1) break;
       T p[KT][2];
 #pragma unroll
-      for (int q = 0; q < KT; q++) {
-        const int k = t0 + q;
-        C v = (in && k < jp1) ? V[(int64_t)k * ldv + e] : mk<C>(0, 0);
-        C pr = cfma_conj(mk<C>(0, 0), v, we);
-        p[q][0] = pr.x;
-        p[q][1] = pr.y;
+      for (int q = 0; q < KT; q++) p[q][0] = p[q][1] = (T)0;
+#pragma unroll
+      for (int i = 0; i < EPT; i++) {
+#pragma unroll
+        for (int q = 0; q < KT; q++) {
+          const int k = t0 + q;
+          const C v = (in[i] && k < jp1) ? V[(int64_t)k * ldv + e[i]] : mk<C>(0, 0);
+          const C pr = cfma_conj(mk<C>(p[q][0], p[q][1]), v, x[i]);
+          p[q][0] = pr.x;
+          p[q][1] = pr.y;
+        }
       }
       wave_reduce_scatter<KT>(p);
       if (lane < KT) {
@@ -109,22 +125,36 @@ __device__ __forceinline__ void cgs_block(int64_t blk, int64_t nblk, const cx<T>
       }
       __syncthreads();
     }
+  };
+  if (MODE == DOTS) {
+    dots(we);
     return;
   }
   // update part (coefficients are uniform: scalar loads)
-  C acc = we;
+  C acc[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; i++) acc[i] = we[i];
 #pragma unroll
   for (int k = 0; k < MAXK; k++) {
     if (k < jp1) {
-      C v = in ? V[(int64_t)k * ldv + e] : mk<C>(0, 0);
       const double2 c = coef[k];
-      acc = cfms(acc, v, mk<C>((T)c.x, (T)c.y));
+      const C ck = mk<C>((T)c.x, (T)c.y);
+#pragma unroll
+      for (int i = 0; i < EPT; i++) {
+        const C v = in[i] ? V[(int64_t)k * ldv + e[i]] : mk<C>(0, 0);
+        acc[i] = cfms(acc[i], v, ck);
+      }
     }
   }
-  if (in) w[e] = acc;
+#pragma unroll
+  for (int i = 0; i < EPT; i++)
+    if (in[i]) w[e[i]] = acc[i];
   if (MODE == UPDATE) return;
   if (MODE == UPNORM) {
-    double s = in ? (double)acc.x * acc.x + (double)acc.y * acc.y : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < EPT; i++)
+      s += in[i] ? (double)acc[i].x * acc[i].x + (double)acc[i].y * acc[i].y : 0.0;
     s = wave_sum(s);
     if (lane == 0) red[wv][0][0] = s;
     __syncthreads();
@@ -133,47 +163,19 @@ __device__ __forceinline__ void cgs_block(int64_t blk, int64_t nblk, const cx<T>
           mk<double2>(red[0][0][0] + red[1][0][0] + red[2][0][0] + red[3][0][0], 0.0);
     return;
   }
-  if (MODE == UPDOTS) {
-    // products with the updated entry, one butterfly per tile of basis
-    // vectors.  The basis entries are read a second time (the wavefront's
-    // lines are still in the caches) rather than held in registers: holding
-    // them halved the occupancy and cost more than the second read.
-    constexpr int KT = MAXK < 32 ? MAXK : 32;
-#pragma unroll 1
-    for (int t0 = 0; t0 < MAXK; t0 += KT) {
-      if (t0 >= jp1) break;
-      T p[KT][2];
-#pragma unroll
-      for (int q = 0; q < KT; q++) {
-        const int k = t0 + q;
-        const C v = (in && k < jp1) ? V[(int64_t)k * ldv + e] : mk<C>(0, 0);
-        C pr = cfma_conj(mk<C>(0, 0), v, acc);
-        p[q][0] = pr.x;
-        p[q][1] = pr.y;
-      }
-      wave_reduce_scatter<KT>(p);
-      if (lane < KT) {
-        red[wv][lane][0] = (double)p[0][0];
-        red[wv][lane][1] = (double)p[0][1];
-      }
-      __syncthreads();
-      if (threadIdx.x < KT && t0 + threadIdx.x < jp1) {
-        const int q = threadIdx.x;
-        double2 s = mk<double2>(red[0][q][0] + red[1][q][0] + red[2][q][0] + red[3][q][0],
-                                red[0][q][1] + red[1][q][1] + red[2][q][1] + red[3][q][1]);
-        partial[(int64_t)(t0 + q) * nblk + blk] = s;
-      }
-      __syncthreads();
-    }
-  }
+  // UPDOTS: products with the updated entries.  The basis entries are read a
+  // second time (the wavefront's lines are still in the caches) rather than
+  // held in registers: holding them halved the occupancy and cost more than
+  // the second read.
+  if (MODE == UPDOTS) dots(acc);
 }
 
-template <typename T, int MAXK, int MODE>
+template <typename T, int MAXK, int MODE, int EPT = 1>
 __global__ __launch_bounds__(256) void cgs_pass(const cx<T> *__restrict__ V, int64_t ldv, int jp1,
                                                  cx<T> *__restrict__ w,
                                                  const double2 *__restrict__ coef,
                                                  double2 *__restrict__ partial, int64_t n) {
-  cgs_block<T, MAXK, MODE>(blockIdx.x, gridDim.x, V, ldv, jp1, w, coef, partial, n);
+  cgs_block<T, MAXK, MODE, EPT>(blockIdx.x, gridDim.x, V, ldv, jp1, w, coef, partial, n);
 }
 
 // Sum partial[k][b] over blocks b (fixed order, FP64); one workgroup per k.
