@@ -31,17 +31,27 @@
 
 namespace dst {
 
+// Norm passes: block b covers [256 kNormEpt b, 256 kNormEpt (b + 1)); each
+// thread sums its kNormEpt elements in order, then the wavefront and the
+// block add theirs.  One element per thread moved too few bytes per
+// workgroup to keep the memory system busy.
+constexpr int kNormEpt = 4;
+static inline unsigned norm_blocks(int64_t n) { return (unsigned)((n + 256 * kNormEpt - 1) / (256 * kNormEpt)); }
+
 // partial[0][b] = sum over the block's elements of |w[e]|^2
 template <typename T>
 __global__ __launch_bounds__(256) void norm_pass(const cx<T> *__restrict__ w,
                                                   double2 *__restrict__ partial, int64_t n) {
   __shared__ double red[4];
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double s = 0.0;
-  if (e < n) {
-    cx<T> v = w[e];
-    s = (double)v.x * v.x + (double)v.y * v.y;
+  cx<T> v[kNormEpt];
+#pragma unroll
+  for (int i = 0; i < kNormEpt; i++) {
+    const int64_t e = ((int64_t)blockIdx.x * kNormEpt + i) * 256 + threadIdx.x;
+    v[i] = e < n ? w[e] : mk<cx<T>>(0, 0);
   }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kNormEpt; i++) s += (double)v[i].x * v[i].x + (double)v[i].y * v[i].y;
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -54,12 +64,18 @@ __global__ __launch_bounds__(256) void norm_pass(const cx<T> *__restrict__ w,
 __global__ __launch_bounds__(256) void norm_pass2(const double2 *__restrict__ x, const double2 *__restrict__ b,
                                                   double2 *__restrict__ partial, int64_t n) {
   __shared__ double red[2][4];
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double2 vx[kNormEpt], vb[kNormEpt];
+#pragma unroll
+  for (int i = 0; i < kNormEpt; i++) {
+    const int64_t e = ((int64_t)blockIdx.x * kNormEpt + i) * 256 + threadIdx.x;
+    vx[i] = e < n ? x[e] : mk<double2>(0, 0);
+    vb[i] = e < n ? b[e] : mk<double2>(0, 0);
+  }
   double sx = 0.0, sb = 0.0;
-  if (e < n) {
-    const double2 vx = x[e], vb = b[e];
-    sx = vx.x * vx.x + vx.y * vx.y;
-    sb = vb.x * vb.x + vb.y * vb.y;
+#pragma unroll
+  for (int i = 0; i < kNormEpt; i++) {
+    sx += vx[i].x * vx[i].x + vx[i].y * vx[i].y;
+    sb += vb[i].x * vb[i].x + vb[i].y * vb[i].y;
   }
   sx = wave_sum(sx);
   sb = wave_sum(sb);
@@ -208,7 +224,6 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   double2 *partial = (double2 *)(work + L.partial);
   Ctrl *ctrl = (Ctrl *)(work + L.ctrl);
   C *Zb = (C *)(work + L.Z);
-  const int64_t nblk = nblocks(N);
   const void *val = sizeof(T) == 8 ? A->val64 : A->val32;
   const bool mf = o->matrix_free != 0;
 
@@ -227,8 +242,8 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   double *const pinned = (double *)readback_buffer(sizeof(local_rb));
   double *const hrb = pinned ? pinned : local_rb;
   auto read_norm = [&](const double2 *v, double &out) -> int {
-    norm_pass<double><<<nblocks(N), 256, 0, s>>>(v, partial, N);
-    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 1, 0);
+    norm_pass<double><<<norm_blocks(N), 256, 0, s>>>(v, partial, N);
+    reduce_partials<<<1, 256, 0, s>>>(partial, norm_blocks(N), ctrl, 1, 0);
     DST_LAUNCHED();
     DST_HIP(hipMemcpyAsync(hrb, &ctrl->dots_norm2, sizeof(double), hipMemcpyDeviceToHost, s));
     DST_HIP(hipStreamSynchronize(s));
@@ -252,8 +267,8 @@ static int gmres_impl(const dirac_st_bsr *A, const double2 *b, double2 *x, const
   double xnorm = 0.0, bnorm = 0.0;
   double2 *rbuf = sizeof(T) == 8 ? (double2 *)V : r64;
   {
-    norm_pass2<<<nblocks(N), 256, 0, s>>>(x, b, partial, N);
-    reduce_partials<<<1, 256, 0, s>>>(partial, nblk, ctrl, 2, 0);
+    norm_pass2<<<norm_blocks(N), 256, 0, s>>>(x, b, partial, N);
+    reduce_partials<<<1, 256, 0, s>>>(partial, norm_blocks(N), ctrl, 2, 0);
     DST_LAUNCHED();
     // the residual of a zero initial guess is b: the copy is queued before the
     // norms are read back, so it runs while the host waits (with a nonzero x
