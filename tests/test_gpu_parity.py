@@ -133,11 +133,16 @@ def test_preconditioners_match_oracle(D, spec, vbar):
     assert np.linalg.norm(zb - zb_or) <= 1e-13 * np.linalg.norm(zb_or)
 
 
-def test_gmres_fp64_matches_oracle_iteration_by_iteration(D):
+@pytest.mark.parametrize("spec", [
+    IN.Spec(d=2, n=[6, 11, 9], vkind=1, v0=2.0, x0=0.5),
+    # 6992 unknowns: several 1024-element blocks of the small-basis passes
+    # and a ragged last block
+    IN.Spec(d=2, n=[8, 23, 19], vkind=1, v0=2.0, x0=0.5),
+], ids=ids)
+def test_gmres_fp64_matches_oracle_iteration_by_iteration(D, spec):
     """Same algorithm (GMRES(m), CGS2, complex Givens, right node-block Jacobi):
     the residual history agrees step by step and the iterate after a fixed
     number of steps matches."""
-    spec = IN.Spec(d=2, n=[6, 11, 9], vkind=1, v0=2.0, x0=0.5)
     A_or = O.Matrix(oprob(spec))
     psi0 = IN.gaussian_packet(spec, [0.3, 0.5], [6.0, 2.0], 0.15, np.array([1, 1]) / np.sqrt(2))
     b_or = A_or.rhs(psi0)
